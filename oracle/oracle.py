@@ -1,0 +1,192 @@
+"""ctypes wrapper of the C++ oracle library (test infrastructure only).
+
+Every array crossing this wrapper is a host numpy float64 array. Fields are
+[ny][nx]; distributions are [16][ny][nx] in the paper's velocity order.
+"""
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lbm_oracle.cpp")
+_LIB = os.path.join(_HERE, "liblbm_oracle.so")
+
+BC_CODES = {"periodic": 0, "zero_gradient": 1, "specular": 2, "neq_wall": 3, "dirichlet_eq": 4}
+
+
+class OracleParams(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32),
+        ("ny", ctypes.c_int32),
+        ("dx", ctypes.c_double),
+        ("dy", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("s", ctypes.c_double * 16),
+        ("eq_version", ctypes.c_int32),
+        ("modified", ctypes.c_int32),
+        ("bc", ctypes.c_int32 * 4),
+        ("wall", (ctypes.c_double * 4) * 4),
+    ]
+
+    @classmethod
+    def from_dict(cls, d):
+        p = cls()
+        p.nx, p.ny = int(d["nx"]), int(d["ny"])
+        p.dx, p.dy, p.dt = float(d["dx"]), float(d["dy"]), float(d["dt"])
+        for k in range(16):
+            p.s[k] = float(d["s"][k])
+        p.eq_version = int(d.get("eq_version", 1))
+        p.modified = int(d.get("modified", 1))
+        for k, b in enumerate(d["bc"]):
+            p.bc[k] = BC_CODES[b] if isinstance(b, str) else int(b)
+        wall = d.get("wall", [[1.0, 0.0, 0.0, 1.0]] * 4)
+        for a in range(4):
+            for b in range(4):
+                p.wall[a][b] = float(wall[a][b])
+        return p
+
+
+def lib_path():
+    return _LIB
+
+
+def build(force=False):
+    """Compile the oracle with g++ (plain -O2, OpenMP over nodes)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared", _SRC, "-o", tmp]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.POINTER(ctypes.c_double)
+        pp = ctypes.POINTER(OracleParams)
+        lib.oracle_matrices.argtypes = [P, P, P]
+        lib.oracle_feq_moments.argtypes = [ctypes.c_int] + [ctypes.c_double] * 4 + [P]
+        lib.oracle_init.argtypes = [pp, P, P, P, P, P]
+        lib.oracle_moments.argtypes = [pp, P, P, P, P, P, P]
+        lib.oracle_run.argtypes = [pp, P, ctypes.c_int64, P, ctypes.c_int]
+        lib.oracle_init_complex.argtypes = [pp] + [P] * 10
+        lib.oracle_run_complex.argtypes = [pp, P, P, P, ctypes.c_int64, P, P, ctypes.c_int]
+        lib.oracle_moments_complex.argtypes = [pp, P, P] + [P] * 8
+        lib.oracle_max_threads.argtypes = []
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _params(p):
+    return p if isinstance(p, OracleParams) else OracleParams.from_dict(p)
+
+
+def max_threads():
+    return int(_load().oracle_max_threads())
+
+
+def matrices():
+    """(V [16,2], M [16,16], M^-1 [16,16]) as used by the oracle."""
+    lib = _load()
+    v = np.zeros((16, 2))
+    m = np.zeros((16, 16))
+    mi = np.zeros((16, 16))
+    lib.oracle_matrices(_ptr(v), _ptr(m), _ptr(mi))
+    return v, m, mi
+
+
+def feq_moments(version, rho, ux, uy, T):
+    out = np.zeros(16)
+    rc = _load().oracle_feq_moments(int(version), float(rho), float(ux), float(uy), float(T), _ptr(out))
+    if rc:
+        raise ValueError("oracle_feq_moments rejected its arguments")
+    return out
+
+
+def init(p, rho, ux, uy, T):
+    p = _params(p)
+    rho, ux, uy, T = (_f64(a) for a in (rho, ux, uy, T))
+    f = np.zeros((16, p.ny, p.nx))
+    if _load().oracle_init(ctypes.byref(p), _ptr(rho), _ptr(ux), _ptr(uy), _ptr(T), _ptr(f)):
+        raise ValueError("oracle_init rejected its arguments")
+    return f
+
+
+def moments(p, f):
+    """dict with rho, ux, uy, T, p."""
+    p = _params(p)
+    f = _f64(f)
+    out = {k: np.zeros((p.ny, p.nx)) for k in ("rho", "ux", "uy", "T", "p")}
+    rc = _load().oracle_moments(
+        ctypes.byref(p), _ptr(f), _ptr(out["rho"]), _ptr(out["ux"]), _ptr(out["uy"]), _ptr(out["T"]), _ptr(out["p"])
+    )
+    if rc:
+        raise ValueError("oracle_moments rejected its arguments")
+    return out
+
+
+def run(p, f, nsteps, nthreads=None):
+    p = _params(p)
+    f = _f64(f)
+    out = np.empty_like(f)
+    nt = max_threads() if nthreads is None else int(nthreads)
+    if _load().oracle_run(ctypes.byref(p), _ptr(f), int(nsteps), _ptr(out), nt):
+        raise ValueError("oracle_run rejected its arguments")
+    return out
+
+
+def init_complex(p, rho, ux, uy, T):
+    p = _params(p)
+    args = []
+    for a in (rho, ux, uy, T):
+        a = np.asarray(a)
+        args += [_f64(a.real), _f64(a.imag)]
+    fr = np.zeros((16, p.ny, p.nx))
+    fi = np.zeros((16, p.ny, p.nx))
+    if _load().oracle_init_complex(ctypes.byref(p), *[_ptr(a) for a in args], _ptr(fr), _ptr(fi)):
+        raise ValueError("oracle_init_complex rejected its arguments")
+    return fr + 1j * fi
+
+
+def run_complex(p, f, nsteps, s_im=None, nthreads=None):
+    p = _params(p)
+    f = np.asarray(f)
+    fr, fi = _f64(f.real), _f64(f.imag)
+    sim = _f64(np.zeros(16) if s_im is None else s_im)
+    outr = np.empty_like(fr)
+    outi = np.empty_like(fr)
+    nt = max_threads() if nthreads is None else int(nthreads)
+    if _load().oracle_run_complex(ctypes.byref(p), _ptr(sim), _ptr(fr), _ptr(fi), int(nsteps), _ptr(outr), _ptr(outi), nt):
+        raise ValueError("oracle_run_complex rejected its arguments")
+    return outr + 1j * outi
+
+
+def moments_complex(p, f):
+    p = _params(p)
+    f = np.asarray(f)
+    fr, fi = _f64(f.real), _f64(f.imag)
+    bufs = [np.zeros((p.ny, p.nx)) for _ in range(8)]
+    if _load().oracle_moments_complex(ctypes.byref(p), _ptr(fr), _ptr(fi), *[_ptr(b) for b in bufs]):
+        raise ValueError("oracle_moments_complex rejected its arguments")
+    names = ("rho", "ux", "uy", "T")
+    return {n: bufs[2 * i] + 1j * bufs[2 * i + 1] for i, n in enumerate(names)}

@@ -1,0 +1,56 @@
+"""Pins of the synthetic workload generators against values the paper prints.
+
+  * Sec. IV.B(b): a Mach 1.22 shock (D = 1.725) into (rho, u, p) = (1, 0, 1)
+    leaves (1.28, -0.3774, 1.6512) behind it; this holds for gamma = 2.
+  * Sec. III and IV.B(a): Ma = u / sqrt(2 T), e.g. 45/sqrt(20) = 10.1.
+"""
+
+import json
+import math
+import os
+
+import numpy as np
+
+from paper_1106_0785_amd import inputs
+from physics import rankine_hugoniot
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_post_shock_state_matches_paper():
+    g = json.load(open(os.path.join(GOLD, "rm_post_shock.json")))
+    rho2, du, p2, D = inputs.post_shock(g["mach"], g["pre"][0], g["pre"][3])
+    assert abs(D - g["D"]) < 5e-4
+    assert abs(rho2 - g["post"][0]) < 5e-3
+    assert abs(-du - g["post"][1]) < 5e-5
+    assert abs(p2 - g["post"][3]) < 5e-5
+    # the generator agrees with an independent textbook jump relation
+    r, u, p, d = rankine_hugoniot(g["mach"], 1.0, 1.0)
+    assert abs(r - rho2) < 1e-12 and abs(u - du) < 1e-12 and abs(p - p2) < 1e-12 and abs(d - D) < 1e-12
+
+
+def test_mach_numbers_match_paper():
+    g = json.load(open(os.path.join(GOLD, "mach_numbers.json")))
+    for c in g["cases"]:
+        ma = abs(c["u"]) / math.sqrt(inputs.GAMMA * c["T"])
+        assert abs(ma - c["Ma"]) <= 0.051 * max(1.0, c["Ma"] / 10), c
+
+
+def test_generators_are_seeded_and_shaped():
+    p1, f1, m1 = inputs.rm(seed=3, nx=128, ny=32)
+    p2, f2, m2 = inputs.rm(seed=3, nx=128, ny=32)
+    for k in f1:
+        assert f1[k].shape == (32, 128)
+        np.testing.assert_array_equal(f1[k], f2[k])
+    assert 1.2 <= m1["mach"] <= 2.0 and 1 <= m1["K"] <= 4
+    # shock sits in the light gas, left of the whole interface
+    assert m1["shock_cells"] < m1["x0_cells"] - np.max(np.abs(m1["a"]))
+    b = inputs.batch(seed=0, n=64)
+    assert len(b) == 64
+    for kind, p, f in b:
+        assert f["rho"].shape == (p["ny"], p["nx"])
+        assert max(p["s"]) * p["dt"] <= 1.0 + 1e-12
+        if kind == "riemann":
+            assert p["ny"] == 1 and 256 <= p["nx"] <= 4096
+        else:
+            assert p["nx"] == 1 and 32 <= p["ny"] <= 256

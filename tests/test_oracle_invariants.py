@@ -1,0 +1,105 @@
+"""Invariant pins of the oracle's time step (Sec. II-III).
+
+  * the collision conserves rho, j, e and the Lax-Wendroff differences
+    telescope, so totals are constant on a periodic grid;
+  * a uniform equilibrium state is a fixed point;
+  * a y-uniform state stays y-uniform, and ny = 1 equals ny = 4;
+  * mirror (x -> -x) and quarter-turn rotation symmetry of the model: the
+    velocity set, M, the equilibria and the modification are isotropic, so a
+    mirrored or rotated initial state evolves into the mirrored or rotated
+    solution. A dropped term or a transposed index in any stage breaks this.
+"""
+
+import numpy as np
+
+import oracle
+from paper_1106_0785_amd import inputs
+
+
+def _totals(p, f):
+    m = oracle.moments(p, f)
+    rho, ux, uy, T = m["rho"], m["ux"], m["uy"], m["T"]
+    return np.array([rho.sum(), (rho * ux).sum(), (rho * uy).sum(), (rho * (T + 0.5 * (ux * ux + uy * uy))).sum()])
+
+
+def test_conservation_periodic():
+    for modified in (0, 1):
+        p, fl = inputs.smooth_periodic(seed=11, nx=32, ny=24, amp=0.08, modified=modified)
+        f0 = oracle.init(p, **fl)
+        f1 = oracle.run(p, f0, 300)
+        assert np.abs(f1 - f0).max() > 1e-3  # the state really evolved
+        t0, t1 = _totals(p, f0), _totals(p, f1)
+        np.testing.assert_allclose(t1, t0, rtol=1e-13, atol=1e-12)
+
+
+def test_uniform_state_is_fixed_point():
+    for ver in (1, 2, 3):
+        p, fl = inputs.smooth_periodic(seed=1, nx=8, ny=6, amp=0.0, eq_version=ver)
+        f0 = oracle.init(p, **fl)
+        f1 = oracle.run(p, f0, 200)
+        assert np.abs(f1 - f0).max() < 1e-14
+
+
+def test_one_dimensional_reduction():
+    p4, fl = inputs.smooth_periodic(seed=5, nx=24, ny=1, amp=0.08)
+    f1d = oracle.init(p4, **fl)
+    r1 = oracle.run(p4, f1d, 150)
+    p4["ny"] = 4
+    f2d = np.repeat(f1d, 4, axis=1)
+    r2 = oracle.run(p4, f2d, 150)
+    for j in range(4):
+        assert np.array_equal(r2[:, j], r1[:, 0])
+
+
+def _mirror_x(f, v):
+    perm = [int(np.where((v[:, 0] == -v[i, 0]) & (v[:, 1] == v[i, 1]))[0][0]) for i in range(16)]
+    return f[perm][:, :, ::-1].copy()
+
+
+def test_mirror_symmetry_with_walls():
+    v, _, _ = oracle.matrices()
+    p, fl = inputs.smooth_periodic(seed=7, nx=20, ny=12, amp=0.08)
+    for bc in (["specular", "specular", "periodic", "periodic"], ["zero_gradient", "zero_gradient", "periodic", "periodic"]):
+        p["bc"] = bc
+        f0 = oracle.init(p, **fl)
+        a = oracle.run(p, f0, 120)
+        b = oracle.run(p, _mirror_x(f0, v), 120)
+        np.testing.assert_allclose(_mirror_x(a, v), b, rtol=0, atol=1e-13)
+
+
+def _rotate(f, v):
+    """Quarter turn: position (x, y) -> (-y, x), velocity (vx, vy) -> (-vy, vx)."""
+    perm = [int(np.where((v[:, 0] == -v[i, 1]) & (v[:, 1] == v[i, 0]))[0][0]) for i in range(16)]
+    g = np.empty((16, f.shape[2], f.shape[1]))
+    for i in range(16):
+        # new[y'=x][x'=ny-1-y] = old[y][x]
+        g[perm[i]] = f[i].T[:, ::-1]
+    return g
+
+
+def test_quarter_turn_symmetry():
+    v, _, _ = oracle.matrices()
+    p, fl = inputs.smooth_periodic(seed=9, nx=18, ny=14, amp=0.08)
+    # isotropy needs s7 = s8, s9 = s10, s15 = s16; s5 and s6 may differ
+    p["s"][4], p["s"][5], p["s"][6], p["s"][7] = 800.0, 1300.0, 1100.0, 1100.0
+    for modified in (0, 1):
+        p["modified"] = modified
+        f0 = oracle.init(p, **fl)
+        a = oracle.run(p, f0, 150)
+        q = dict(p, nx=p["ny"], ny=p["nx"])
+        b = oracle.run(q, _rotate(f0, v), 150)
+        np.testing.assert_allclose(_rotate(a, v), b, rtol=0, atol=1e-13)
+
+
+def test_printed_q8_sign_breaks_isotropy():
+    """The Q_8 normal-stress term exactly as printed (modified = 2) is not the
+    quarter-turn image of the Q_7 term, so the rotated run differs."""
+    v, _, _ = oracle.matrices()
+    p, fl = inputs.smooth_periodic(seed=9, nx=18, ny=14, amp=0.08)
+    p["s"][4], p["s"][5], p["s"][6], p["s"][7] = 800.0, 1300.0, 1100.0, 1100.0
+    p["modified"] = 2
+    f0 = oracle.init(p, **fl)
+    a = oracle.run(p, f0, 150)
+    q = dict(p, nx=p["ny"], ny=p["nx"])
+    b = oracle.run(q, _rotate(f0, v), 150)
+    assert np.abs(_rotate(a, v) - b).max() > 1e-9
