@@ -1,0 +1,178 @@
+"""Benchmark of the MRT FD-LBM hot path on one MI355X.
+
+Prints ONE JSON line. The headline workload is the Richtmyer-Meshkov-shaped
+problem at 4096 x 1024 nodes (HBM-resident: 2 x 537 MB of distributions, far
+beyond the 256 MB Infinity Cache): one step = one time step of every node
+(moments, equilibria, relaxation with the energy-flux modification,
+back-transform, Lax-Wendroff convection, store). value = MLUPS (million node
+updates per second) with the state resident in HBM. The roofline object
+prices the step kernel against the 8 TB/s HBM peak with 256 algorithmic
+bytes per node update (16 FP64 loads + 16 FP64 stores). Side results: the
+1024 x 256 problem itself, the paper's small configurations, and the oracle
+timed on the host cores.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12  # bytes/s, MI355X HBM3E
+BYTES_PER_NODE = 256  # 16 FP64 reads + 16 FP64 writes per node update
+KERNEL_SOURCES = ["paper_1106_0785_amd/csrc/lbm_kernels.h", "paper_1106_0785_amd/csrc/lbm_step.h",
+                  "paper_1106_0785_amd/csrc/lbm_node.h", "paper_1106_0785_amd/csrc/lbm_consts.h"]
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for s in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, s), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def time_steps(sim, steps, warmup):
+    import torch
+
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    sim.step(steps)
+    stop.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / 1e3  # seconds
+
+
+def run_problem(p, fields, steps, warmup, rows=None):
+    from paper_1106_0785_amd import lbm
+
+    sim = lbm.Simulation(p)
+    if rows:
+        sim.set_tile(rows)
+    sim.init(**fields)
+    t = time_steps(sim, steps, warmup)
+    sim.check()
+    nodes = p["nx"] * p["ny"]
+    sim.close()
+    return {"seconds": t, "steps": steps, "nodes": nodes, "mlups": nodes * steps / t / 1e6,
+            "ms_per_step": 1e3 * t / steps, "gbps": nodes * steps * BYTES_PER_NODE / t / 1e9}
+
+
+def traffic_from_profiles(kernel_name, workload):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, if
+    they were taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+        e = d.get(workload)
+        if e and e.get("kernel_hash") == kernel_hash() and e.get("kernel") == kernel_name:
+            return e["bytes_per_launch"]
+    except Exception:
+        return None
+    return None
+
+
+def cpu_baseline(budget_s=15.0):
+    """The oracle as it stands, on the host cores, on a bounded sample of the
+    1024 x 256 shock/interface problem."""
+    import oracle
+    from paper_1106_0785_amd import inputs
+
+    p, fl, _ = inputs.rm(seed=0, nx=1024, ny=256)
+    f = oracle.init(p, **fl)
+    nt = oracle.max_threads()
+    t0 = time.perf_counter()
+    f = oracle.run(p, f, 1, nthreads=nt)
+    one = time.perf_counter() - t0
+    n = max(1, int(budget_s / max(one, 1e-6)))
+    t0 = time.perf_counter()
+    oracle.run(p, f, n, nthreads=nt)
+    t = time.perf_counter() - t0
+    return {"value": 1024 * 256 * n / t / 1e6, "unit": "MLUPS", "cores": nt, "kind": "oracle",
+            "sample": "1024x256 shock/interface problem, %d time steps after 1 warm-up step (%.1f s)" % (n, t)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--quick", action="store_true", help="headline workload only")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build runs on a single MI355X (no multi-GPU path); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1106_0785_amd import inputs, lbm
+
+    lbm.load()
+    torch.cuda.set_device(0)
+
+    # headline: HBM-resident RM-shaped problem
+    nx, ny = 4096, 1024
+    p, fl, _ = inputs.rm(seed=0, nx=nx, ny=ny)
+    log("headline rm %dx%d: %d warm-up + %d timed steps" % (nx, ny, args.warmup, args.steps))
+    head = run_problem(p, fl, args.steps, args.warmup)
+    extra = {}
+    if not args.quick:
+        p3, fl3, _ = inputs.rm(seed=0, nx=1024, ny=256)
+        log("rm 1024x256")
+        extra["rm_1024x256"] = run_problem(p3, fl3, 1000, 50)
+        pc, flc, _ = inputs.couette(1.0)
+        log("couette 4x64")
+        extra["couette_4x64"] = run_problem(pc, flc, 2000, 100)
+        pr, flr, _ = inputs.riemann("sod", nx=2000, ny=4)
+        log("riemann 2000x4")
+        extra["riemann_2000x4"] = run_problem(pr, flr, 2000, 100)
+
+    kernel = "k_step_fused"
+    workload = "rm_%dx%d" % (nx, ny)
+    bytes_per_launch = BYTES_PER_NODE * nx * ny
+    achieved = bytes_per_launch / (head["seconds"] / head["steps"]) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                "frac": round(achieved * 1e9 / HBM_PEAK, 4), "traffic": traffic_from_profiles(kernel, workload),
+                "kernel": kernel, "algorithmic_bytes_per_launch": bytes_per_launch}
+    out = {
+        "metric": "MLUPS (FP64 node updates/s) and fraction of HBM roofline",
+        "value": round(head["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": workload, "nx": nx, "ny": ny, "problem": "planar shock on a perturbed light/heavy "
+                   "interface, reflecting x walls, periodic y, Pr 0.71", "parallelism": "single GPU"},
+        "roofline": roofline,
+        "extra": extra,
+        "kernel_hash": kernel_hash(),
+    }
+    if not args.no_cpu:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

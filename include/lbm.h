@@ -1,0 +1,143 @@
+/*
+ * liblbm -- C ABI of the MI355X (gfx950) implementation of the compressible
+ * two-dimensional 16-velocity multiple-relaxation-time finite-difference
+ * lattice Boltzmann model with the energy-flux collision modification
+ * (Chen, Xu, Zhang, Li: "Prandtl number effects in MRT lattice Boltzmann
+ * models for shocked and unshocked compressible fluids").
+ *
+ * Conventions shared by every entry point
+ *   - Units are the paper's non-dimensional ones with R = 1 (Sec. IV): the
+ *     velocities are cyc(+-1,0), (+-1,+-1), cyc(+-2,0), (+-2,+-2) (Sec. II,
+ *     Fig. 1), the gas has e = rho (T + u^2/2) and p = rho T.
+ *   - Distributions are FP64, 16 planes in the paper's velocity order.
+ *     Dense field arrays passed in or out are row-major [ny][nx] (x fastest);
+ *     dense distribution arrays are [16][ny][nx].
+ *   - Every pointer named d_* is device memory on the device that was
+ *     current when the handle was created; the caller owns it, the library
+ *     never frees caller memory.
+ *   - Every call only enqueues work on the handle's HIP stream (asynchronous
+ *     with respect to the host) unless its comment says it synchronises.
+ *   - Errors are returned as lbm_status; lbm_last_error() then holds a
+ *     message for the calling thread. No call aborts or throws.
+ */
+#ifndef LBM_H_
+#define LBM_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,      /* invalid argument (message says which) */
+  LBM_ENOMEM = -2,      /* workspace too small */
+  LBM_EHIP = -3,        /* a HIP runtime call failed */
+  LBM_ESTATE = -4,      /* call not valid in the handle's current state */
+  LBM_ENONFINITE = -5   /* the device health flag saw rho <= 0, T <= 0 or NaN */
+} lbm_status;
+
+/* Boundary kind of one side of the domain. */
+typedef enum {
+  LBM_BC_PERIODIC = 0,      /* wrap; both sides of the axis must be periodic */
+  LBM_BC_ZERO_GRADIENT = 1, /* ghost = boundary node (extrapolation outflow, Sec. IV.B(b)) */
+  LBM_BC_SPECULAR = 2,      /* ghost = boundary node with the normal velocity
+                               component negated (reflecting wall, Sec. IV.B(b)) */
+  LBM_BC_NEQ_WALL = 3,      /* non-equilibrium extrapolation wall on the first/last
+                               node of the axis (Sec. IV.A); uses wall[side] = (-, ux, uy, T) */
+  LBM_BC_DIRICHLET_EQ = 4   /* ghost = equilibrium of the fixed state wall[side] =
+                               (rho, ux, uy, T) (fixed inflow, Sec. IV.B(b)) */
+} lbm_bc;
+
+/* Sides, in the order of lbm_params.bc and lbm_params.wall. */
+enum { LBM_SIDE_XLO = 0, LBM_SIDE_XHI = 1, LBM_SIDE_YLO = 2, LBM_SIDE_YHI = 3 };
+
+/* Problem description (Sec. II-IV).
+ *   nx, ny      nodes; an axis of extent 1 must be periodic (exact 1-D problem)
+ *   dx, dy, dt  grid spacings and time step (> 0)
+ *   s[16]       relaxation rates s_1..s_16 of the diagonal S^ (Sec. II, Eq. 3);
+ *               s_1..s_4 act on conserved moments and have no effect
+ *   eq_version  free equilibrium moments 12, 15, 16 (Sec. II): 1 zeros,
+ *               2 the printed polynomials, 3 moments of the sampled Maxwellian
+ *   modified    0: unmodified collision; 1: energy-flux modification with the
+ *               Q_8 normal-stress term u_y (d_y u_y - d_x u_x), for which the
+ *               recovered energy equation is Eq. (5); 2: the same modification
+ *               with that term's sign exactly as printed (Sec. II)
+ *   bc[4]       lbm_bc per side (x_lo, x_hi, y_lo, y_hi); NEQ walls may be on
+ *               one axis only and that axis needs >= 3 nodes
+ *   wall[4][4]  per side (rho, ux, uy, T), used by NEQ_WALL and DIRICHLET_EQ */
+typedef struct {
+  int32_t nx, ny;
+  double dx, dy, dt;
+  double s[16];
+  int32_t eq_version;
+  int32_t modified;
+  int32_t bc[4];
+  double wall[4][4];
+} lbm_params;
+
+typedef struct lbm_handle lbm_handle;
+
+/* Bytes of device workspace lbm_create needs for p: two pitched
+ * distribution buffers [16][ny][pitch] (pitch = nx rounded up to 64 doubles)
+ * and a small status block, 256-byte aligned. 0 if p is invalid. */
+size_t lbm_workspace_bytes(const lbm_params* p);
+
+/* Validates p and binds a handle to caller-owned workspace d_workspace
+ * (>= lbm_workspace_bytes(p) bytes, 256-byte aligned) and to hip_stream
+ * (a hipStream_t, or NULL for the null stream). Rejects with LBM_EINVAL:
+ * nx or ny < 1, dx, dy or dt <= 0, s_k <= 0 for k >= 5, max_k s_k dt > 2
+ * (explicit relaxation unstable), unpaired periodic sides, NEQ walls on both
+ * axes or on an axis with < 3 nodes, eq_version not in {1,2,3}, modified not
+ * in {0,1,2}; LBM_ENOMEM if ws_bytes is too small. The handle owns only host
+ * metadata. */
+lbm_status lbm_create(const lbm_params* p, void* d_workspace, size_t ws_bytes, void* hip_stream,
+                      lbm_handle** out);
+
+/* Initial state f = M^-1 f^eq(rho, u, T) at every node (Sec. II equilibria,
+ * Eqs. 14a-14i, with the handle's eq_version). Inputs are device [ny][nx]. */
+lbm_status lbm_init(lbm_handle* h, const double* d_rho, const double* d_ux, const double* d_uy,
+                    const double* d_T);
+
+/* Advance nsteps >= 0 time steps of Eq. (3): per node, moments f^ = M f,
+ * Q_k = s_k (f^_k - f^eq_k) plus the energy-flux modification of Q_7, Q_8
+ * (Sec. II), collision -dt M^-1 Q, and per-axis central Lax-Wendroff
+ * convection with forward-Euler time stepping (the scheme whose amplification
+ * matrix is G_ij, Sec. III). Velocity gradients in the modification are
+ * central differences of nodal velocities at the old time level. */
+lbm_status lbm_step(lbm_handle* h, int64_t nsteps);
+
+/* rho, u_x, u_y, T = e/rho - u^2/2 and p = rho T of the current state
+ * (Sec. II, conserved moments; R = 1). Device [ny][nx]; any may be NULL. */
+lbm_status lbm_moments(lbm_handle* h, double* d_rho, double* d_ux, double* d_uy, double* d_T, double* d_p);
+
+/* Copy the current distributions to / from a dense device array [16][ny][nx]
+ * (checkpoint and restore: f and the parameters determine the state). */
+lbm_status lbm_get_f(lbm_handle* h, double* d_f);
+lbm_status lbm_set_f(lbm_handle* h, const double* d_f);
+
+/* Synchronises the stream and reads the device health flag: LBM_OK, or
+ * LBM_ENONFINITE if any step since the last check produced rho <= 0,
+ * T <= 0 or a NaN; the flag is then cleared. */
+lbm_status lbm_check(lbm_handle* h);
+
+/* Kernel variant used by lbm_step: 0 = the fused LDS-staged kernel (default),
+ * 1 = the plain one-thread-per-node global-memory kernel (a reference for
+ * race and indexing checks). Rows per workgroup tile for variant 0 via
+ * lbm_set_tile (power of two, 1..16). */
+lbm_status lbm_set_variant(lbm_handle* h, int32_t variant);
+lbm_status lbm_set_tile(lbm_handle* h, int32_t rows);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* lbm_last_error(void);
+
+/* Releases the handle (NULL-safe); does not touch the workspace. */
+void lbm_destroy(lbm_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H_ */

@@ -1,0 +1,327 @@
+// C ABI of the single-problem path (declarations and contracts in include/lbm.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/lbm.h"
+#include "lbm_internal.h"
+
+using namespace lbm;
+
+namespace {
+thread_local std::string g_err;
+}
+
+namespace lbm {
+
+lbm_status fail(lbm_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+lbm_status hip_fail(hipError_t e, const char* what) {
+  return fail(LBM_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+void clear_error() { g_err.clear(); }
+
+long long row_pitch(int nx) { return ((long long)nx + 63) / 64 * 64; }
+
+bool has_walls(const lbm_params* p) {
+  for (int k = 0; k < 4; ++k)
+    if (p->bc[k] == LBM_BC_NEQ_WALL) return true;
+  return false;
+}
+
+size_t consts_bytes() { return (sizeof(Consts) + 255) / 256 * 256; }
+
+lbm_status validate(const lbm_params* p) {
+  if (!p) return fail(LBM_EINVAL, "params is NULL");
+  if (p->nx < 1 || p->ny < 1) return fail(LBM_EINVAL, "nx and ny must be >= 1 (got %d x %d)", p->nx, p->ny);
+  if ((long long)p->nx * p->ny > (1LL << 31)) return fail(LBM_EINVAL, "grid too large");
+  if (!(p->dx > 0) || !(p->dy > 0) || !(p->dt > 0)) return fail(LBM_EINVAL, "dx, dy, dt must be > 0");
+  double smax = 0;
+  for (int k = 4; k < 16; ++k) {
+    if (!(p->s[k] > 0)) return fail(LBM_EINVAL, "s_%d must be > 0", k + 1);
+    smax = std::max(smax, p->s[k]);
+  }
+  if (smax * p->dt > 2.0)
+    return fail(LBM_EINVAL, "max_k s_k dt = %g > 2: the explicit relaxation is unstable", smax * p->dt);
+  if (p->eq_version < 1 || p->eq_version > 3) return fail(LBM_EINVAL, "eq_version must be 1, 2 or 3");
+  if (p->modified < 0 || p->modified > 2) return fail(LBM_EINVAL, "modified must be 0, 1 or 2");
+  for (int k = 0; k < 4; ++k)
+    if (p->bc[k] < 0 || p->bc[k] > 4) return fail(LBM_EINVAL, "bc[%d] = %d is not a boundary kind", k, p->bc[k]);
+  for (int a = 0; a < 2; ++a)
+    if ((p->bc[2 * a] == LBM_BC_PERIODIC) != (p->bc[2 * a + 1] == LBM_BC_PERIODIC))
+      return fail(LBM_EINVAL, "periodic boundaries must be paired on an axis");
+  const bool xw = p->bc[0] == LBM_BC_NEQ_WALL || p->bc[1] == LBM_BC_NEQ_WALL;
+  const bool yw = p->bc[2] == LBM_BC_NEQ_WALL || p->bc[3] == LBM_BC_NEQ_WALL;
+  if (xw && yw) return fail(LBM_EINVAL, "NEQ walls on both axes are not supported");
+  if (xw && p->nx < 3) return fail(LBM_EINVAL, "NEQ walls on x need nx >= 3");
+  if (yw && p->ny < 3) return fail(LBM_EINVAL, "NEQ walls on y need ny >= 3");
+  if (p->nx == 1 && p->bc[0] != LBM_BC_PERIODIC) return fail(LBM_EINVAL, "an axis of extent 1 must be periodic");
+  if (p->ny == 1 && p->bc[2] != LBM_BC_PERIODIC) return fail(LBM_EINVAL, "an axis of extent 1 must be periodic");
+  for (int sd = 0; sd < 4; ++sd) {
+    if (p->bc[sd] == LBM_BC_DIRICHLET_EQ && (!(p->wall[sd][0] > 0) || !(p->wall[sd][3] > 0)))
+      return fail(LBM_EINVAL, "fixed-state side %d needs rho > 0 and T > 0", sd);
+    if (p->bc[sd] == LBM_BC_NEQ_WALL && !(p->wall[sd][3] > 0))
+      return fail(LBM_EINVAL, "wall side %d needs T > 0", sd);
+  }
+  return LBM_OK;
+}
+
+void make_coef(const lbm_params* p, Hot* c, Cold* cold) {
+  std::memset(c, 0, sizeof(*c));
+  std::memset(cold, 0, sizeof(*cold));
+  const double dt = p->dt;
+  for (int k = 4; k < 16; ++k) c->cq[k - 4] = -dt * p->s[k];
+  if (p->modified) {
+    const double s5 = p->s[4], s6 = p->s[5], s7 = p->s[6], s8 = p->s[7];
+    const double sgn = (p->modified == 2) ? 1.0 : -1.0;
+    c->cmod[0] = -dt * (s7 / s5 - 1.0);
+    c->cmod[1] = -dt * (s7 / s6 - 1.0);
+    c->cmod[2] = -dt * (s8 / s6 - 1.0);
+    c->cmod[3] = -dt * sgn * (s8 / s5 - 1.0);
+  }
+  c->inv2dx = 1.0 / (2.0 * p->dx);
+  c->inv2dy = 1.0 / (2.0 * p->dy);
+  const double rx = dt / p->dx, ry = dt / p->dy;
+  for (int v = 1; v <= 2; ++v) {
+    const double cx = v * rx, cy = v * ry;
+    c->lx[2 * (v - 1)] = 0.5 * cx * cx - 0.5 * cx;
+    c->lx[2 * (v - 1) + 1] = 0.5 * cx * cx + 0.5 * cx;
+    c->ly[2 * (v - 1)] = 0.5 * cy * cy - 0.5 * cy;
+    c->ly[2 * (v - 1) + 1] = 0.5 * cy * cy + 0.5 * cy;
+  }
+  const int ax[6] = {1, 0, 1, 2, 0, 2}, ay[6] = {0, 1, 1, 0, 2, 2};
+  for (int j = 0; j < 6; ++j) {
+    const double cx = ax[j] * rx, cy = ay[j] * ry;
+    c->c0[j] = 1.0 - cx * cx - cy * cy;
+  }
+  for (int sd = 0; sd < 4; ++sd) {
+    for (int j = 0; j < 4; ++j) cold->wall[sd][j] = p->wall[sd][j];
+    if (p->bc[sd] == LBM_BC_DIRICHLET_EQ)
+      equilibrium_f(p->eq_version, p->wall[sd][0], p->wall[sd][1], p->wall[sd][2], p->wall[sd][3], cold->ghost[sd]);
+    c->bc[sd] = p->bc[sd];
+  }
+  c->version = p->eq_version;
+  c->modified = p->modified;
+}
+
+MarchGeom march_geom(int nx, int ny, int rows) {
+  MarchGeom g;
+  g.nstrips = (nx + STRIP - 1) / STRIP;
+  rows = std::max(WAVES, std::min(rows, (ny + WAVES - 1) / WAVES * WAVES));
+  g.rows = (rows + WAVES - 1) / WAVES * WAVES;
+  g.nsegs = (ny + g.rows - 1) / g.rows;
+  g.ntiles = g.nstrips * g.nsegs;
+  g.per_xcd = (g.ntiles + 7) / 8;
+  return g;
+}
+
+hipError_t launch_step(const Field& F, const Hot* c, const Cold* cold, int version, bool walls, int variant,
+                       int rows, int* flag, hipStream_t s) {
+  if (variant == 1) {
+    dim3 block(64, 4);
+    dim3 grid((F.nx + 63) / 64, (F.ny + 3) / 4);
+    auto k = version == 2 ? k_step_plain<2> : version == 3 ? k_step_plain<3> : k_step_plain<1>;
+    hipLaunchKernelGGL(k, grid, block, 0, s, F, c, cold, flag);
+  } else {
+    const MarchGeom g = march_geom(F.nx, F.ny, rows);
+    decltype(&k_step_fused<1, false>) k;
+    if (walls)
+      k = version == 2 ? k_step_fused<2, true> : version == 3 ? k_step_fused<3, true> : k_step_fused<1, true>;
+    else
+      k = version == 2 ? k_step_fused<2, false> : version == 3 ? k_step_fused<3, false> : k_step_fused<1, false>;
+    hipLaunchKernelGGL(k, dim3(8 * g.per_xcd), dim3(64 * WAVES), 0, s, F, c, cold, g, flag);
+  }
+  return hipGetLastError();
+}
+
+int default_rows(int nx, int ny) {
+  // tall tiles amortise the two halo rows; keep at least ~2 workgroups per CU
+  const long long strips = (nx + STRIP - 1) / STRIP;
+  int rows = 64;
+  while (rows > WAVES && strips * ((ny + rows - 1) / rows) < 1024) rows /= 2;
+  return rows;
+}
+
+}  // namespace lbm
+
+struct lbm_handle {
+  lbm_params p;
+  Consts host;   // coefficients (host copy)
+  Consts* dev;   // device copy (in the workspace)
+  hipStream_t stream;
+  int device;
+  double* f[2];
+  int cur;
+  int* flag;
+  long long pitch, plane;
+  int variant;
+  int rows;
+};
+
+static Field field_of(const lbm_handle* h, int from) {
+  Field F;
+  F.fin = h->f[from];
+  F.fout = h->f[from ^ 1];
+  F.nx = h->p.nx;
+  F.ny = h->p.ny;
+  F.pitch = h->pitch;
+  F.plane = h->plane;
+  return F;
+}
+
+extern "C" {
+
+size_t lbm_workspace_bytes(const lbm_params* p) {
+  if (validate(p) != LBM_OK) return 0;
+  const long long plane = row_pitch(p->nx) * p->ny;
+  return (size_t)(2 * 16 * plane * sizeof(double)) + 256 + consts_bytes();
+}
+
+lbm_status lbm_create(const lbm_params* p, void* d_workspace, size_t ws_bytes, void* hip_stream,
+                      lbm_handle** out) {
+  if (!out) return fail(LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  lbm_status st = validate(p);
+  if (st != LBM_OK) return st;
+  const size_t need = lbm_workspace_bytes(p);
+  if (!d_workspace) return fail(LBM_EINVAL, "workspace is NULL");
+  if (((uintptr_t)d_workspace) % 256) return fail(LBM_EINVAL, "workspace must be 256-byte aligned");
+  if (ws_bytes < need) return fail(LBM_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+  lbm_handle* h = new (std::nothrow) lbm_handle;
+  if (!h) return fail(LBM_ENOMEM, "host allocation failed");
+  h->p = *p;
+  make_coef(p, &h->host.hot, &h->host.cold);
+  h->stream = (hipStream_t)hip_stream;
+  hipError_t e = hipGetDevice(&h->device);
+  if (e != hipSuccess) {
+    delete h;
+    return hip_fail(e, "hipGetDevice");
+  }
+  h->pitch = row_pitch(p->nx);
+  h->plane = h->pitch * p->ny;
+  char* base = (char*)d_workspace;
+  h->f[0] = (double*)base;
+  h->f[1] = (double*)(base + 16 * h->plane * sizeof(double));
+  h->flag = (int*)(base + 2 * 16 * h->plane * sizeof(double));
+  h->dev = (Consts*)(base + 2 * 16 * h->plane * sizeof(double) + 256);
+  h->cur = 0;
+  h->variant = 0;
+  h->rows = default_rows(p->nx, p->ny);
+  e = hipMemsetAsync(h->flag, 0, 256, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h->dev, &h->host, sizeof(Consts), hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);  // the host copy source is the handle
+  if (e != hipSuccess) {
+    delete h;
+    return hip_fail(e, "uploading the problem constants");
+  }
+  *out = h;
+  clear_error();
+  return LBM_OK;
+}
+
+lbm_status lbm_init(lbm_handle* h, const double* d_rho, const double* d_ux, const double* d_uy, const double* d_T) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (!d_rho || !d_ux || !d_uy || !d_T) return fail(LBM_EINVAL, "initial fields must not be NULL");
+  Field F = field_of(h, h->cur ^ 1);  // write into the current buffer
+  dim3 grid((h->p.nx + 63) / 64, h->p.ny);
+  auto k = h->p.eq_version == 2 ? k_init<2> : h->p.eq_version == 3 ? k_init<3> : k_init<1>;
+  hipLaunchKernelGGL(k, grid, dim3(64), 0, h->stream, F, d_rho, d_ux, d_uy, d_T);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "k_init launch");
+  // the other buffer gets the same state so wall nodes are defined in both
+  e = hipMemcpyAsync(h->f[h->cur ^ 1], h->f[h->cur], 16 * h->plane * sizeof(double), hipMemcpyDeviceToDevice,
+                     h->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+  return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_handle* h, int64_t nsteps) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
+  for (int64_t n = 0; n < nsteps; ++n) {
+    hipError_t e =
+        launch_step(field_of(h, h->cur), &h->dev->hot, &h->dev->cold, h->p.eq_version, has_walls(&h->p), h->variant,
+                    h->rows, h->flag, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "step kernel launch");
+    h->cur ^= 1;
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_moments(lbm_handle* h, double* d_rho, double* d_ux, double* d_uy, double* d_T, double* d_p) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  Field F = field_of(h, h->cur);
+  dim3 grid((h->p.nx + 63) / 64, h->p.ny);
+  hipLaunchKernelGGL(k_moments, grid, dim3(64), 0, h->stream, F, d_rho, d_ux, d_uy, d_T, d_p);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "k_moments launch");
+  return LBM_OK;
+}
+
+lbm_status lbm_get_f(lbm_handle* h, double* d_f) {
+  if (!h || !d_f) return fail(LBM_EINVAL, "NULL argument");
+  hipError_t e = hipMemcpy2DAsync(d_f, h->p.nx * sizeof(double), h->f[h->cur], h->pitch * sizeof(double),
+                                  h->p.nx * sizeof(double), (size_t)16 * h->p.ny, hipMemcpyDeviceToDevice, h->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy2DAsync");
+  return LBM_OK;
+}
+
+lbm_status lbm_set_f(lbm_handle* h, const double* d_f) {
+  if (!h || !d_f) return fail(LBM_EINVAL, "NULL argument");
+  for (int b = 0; b < 2; ++b) {
+    hipError_t e = hipMemcpy2DAsync(h->f[b], h->pitch * sizeof(double), d_f, h->p.nx * sizeof(double),
+                                    h->p.nx * sizeof(double), (size_t)16 * h->p.ny, hipMemcpyDeviceToDevice,
+                                    h->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy2DAsync");
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_check(lbm_handle* h) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  int flag = 0;
+  hipError_t e = hipMemcpyAsync(&flag, h->flag, sizeof(int), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(e, "reading the health flag");
+  if (flag) {
+    e = hipMemsetAsync(h->flag, 0, sizeof(int), h->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
+    return fail(LBM_ENONFINITE, "a step produced rho <= 0, T <= 0 or NaN");
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_set_variant(lbm_handle* h, int32_t variant) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (variant != 0 && variant != 1) return fail(LBM_EINVAL, "variant must be 0 or 1");
+  h->variant = variant;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_tile(lbm_handle* h, int32_t rows) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (rows < 1 || rows > 1024) return fail(LBM_EINVAL, "rows must be in 1..1024");
+  h->rows = rows;
+  return LBM_OK;
+}
+
+const char* lbm_last_error(void) { return g_err.c_str(); }
+
+void lbm_destroy(lbm_handle* h) { delete h; }
+
+}  // extern "C"

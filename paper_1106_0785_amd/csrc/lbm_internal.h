@@ -1,0 +1,31 @@
+// Library-internal helpers shared by the single-problem, batched and adjoint
+// entry points (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/lbm.h"
+#include "lbm_kernels.h"
+
+namespace lbm {
+
+lbm_status fail(lbm_status s, const char* fmt, ...);
+lbm_status hip_fail(hipError_t e, const char* what);
+void clear_error();
+long long row_pitch(int nx);
+lbm_status validate(const lbm_params* p);
+// Coefficients of one problem as stored in device memory.
+struct Consts {
+  Hot hot;
+  Cold cold;
+};
+
+size_t consts_bytes();
+void make_coef(const lbm_params* p, Hot* c, Cold* cold);
+MarchGeom march_geom(int nx, int ny, int rows);
+bool has_walls(const lbm_params* p);
+hipError_t launch_step(const Field& F, const Hot* c, const Cold* cold, int version, bool walls, int variant,
+                       int rows, int* flag, hipStream_t s);
+int default_rows(int nx, int ny);
+
+}  // namespace lbm

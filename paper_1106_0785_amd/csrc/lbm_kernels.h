@@ -1,0 +1,328 @@
+// Step kernels of one problem: the fused row-marching kernel and the plain
+// one-thread-per-node reference kernel, plus init / moments kernels.
+#pragma once
+
+#include "lbm_step.h"
+
+namespace lbm {
+
+// Launch-time view of one problem's distributions.
+struct Field {
+  const double* __restrict__ fin;
+  double* __restrict__ fout;
+  int nx, ny;
+  long long pitch;  // doubles between rows
+  long long plane;  // doubles between velocity planes
+};
+
+// Ghost-aware source of a stencil point along one axis: index actually read
+// and how its velocities are treated (0 as stored, 1 mirrored, 2 replaced by
+// the equilibrium ghost of side `side`).
+struct Src {
+  int idx;
+  int mode;
+  int side;
+};
+
+LBM_HD Src resolve(int i, int n, int bc_lo, int bc_hi, int side_lo) {
+  Src s{i, 0, -1};
+  if (i < 0) {
+    s.side = side_lo;
+    switch (bc_lo) {
+      case BC_PERIODIC: s.idx = i + n; break;
+      case BC_SPECULAR: s.idx = 0; s.mode = 1; break;
+      case BC_DIRICHLET_EQ: s.idx = 0; s.mode = 2; break;
+      default: s.idx = 0; break;  // zero-gradient; a NEQ-wall side's ghost is never used
+    }
+  } else if (i >= n) {
+    s.side = side_lo + 1;
+    switch (bc_hi) {
+      case BC_PERIODIC: s.idx = i - n; break;
+      case BC_SPECULAR: s.idx = n - 1; s.mode = 1; break;
+      case BC_DIRICHLET_EQ: s.idx = n - 1; s.mode = 2; break;
+      default: s.idx = n - 1; break;
+    }
+  }
+  return s;
+}
+
+// Distributions of the stencil point (column sx, row sy) after ghost resolution.
+__device__ __forceinline__ void load_point(const Field& F, const Cold* __restrict__ cold, const Src& sx, const Src& sy,
+                                           double* f) {
+  const double* p = F.fin + (long long)sy.idx * F.pitch + sx.idx;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) f[i] = p[i * F.plane];
+  if (__builtin_expect((sx.mode | sy.mode) != 0, 0)) {
+    if (sx.mode == 2 || sy.mode == 2) {
+      const int side = (sx.mode == 2) ? sx.side : sy.side;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) f[i] = cold->ghost[side][i];
+    } else {
+      double t[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) t[i] = f[i];
+      if (sy.mode == 1) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) f[i] = t[MIRROR_Y[i]];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) t[i] = f[i];
+      }
+      if (sx.mode == 1) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) f[i] = t[MIRROR_X[i]];
+      }
+    }
+  }
+}
+
+LBM_HD bool is_wall_node(const Hot& c, int x, int y, int nx, int ny) {
+  return (c.bc[0] == BC_NEQ_WALL && x == 0) || (c.bc[1] == BC_NEQ_WALL && x == nx - 1) ||
+         (c.bc[2] == BC_NEQ_WALL && y == 0) || (c.bc[3] == BC_NEQ_WALL && y == ny - 1);
+}
+
+__device__ __forceinline__ void store_node(const Field& F, int x, int y, const double* v) {
+  double* p = F.fout + (long long)y * F.pitch + x;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) p[i * F.plane] = v[i];
+}
+
+// Writes the NEQ wall node(s) fed by interior node (x, y) whose new
+// distributions are `out`.
+template <int VER>
+__device__ __forceinline__ void walls_from(const Field& F, const Hot& c, const Cold* __restrict__ cold, int x, int y,
+                                           const double* out) {
+  const bool lo_y = c.bc[2] == BC_NEQ_WALL && y == 1;
+  const bool hi_y = c.bc[3] == BC_NEQ_WALL && y == F.ny - 2;
+  const bool lo_x = c.bc[0] == BC_NEQ_WALL && x == 1;
+  const bool hi_x = c.bc[1] == BC_NEQ_WALL && x == F.nx - 2;
+  if (__builtin_expect(lo_y | hi_y | lo_x | hi_x, 0)) {
+    double fw[16];
+    if (lo_y) {
+      neq_wall<VER>(cold->wall[2], out, fw);
+      store_node(F, x, 0, fw);
+    }
+    if (hi_y) {
+      neq_wall<VER>(cold->wall[3], out, fw);
+      store_node(F, x, F.ny - 1, fw);
+    }
+    if (lo_x) {
+      neq_wall<VER>(cold->wall[0], out, fw);
+      store_node(F, 0, y, fw);
+    }
+    if (hi_x) {
+      neq_wall<VER>(cold->wall[1], out, fw);
+      store_node(F, F.nx - 1, y, fw);
+    }
+  }
+}
+
+// Copies the problem coefficients into LDS. Reading them from LDS at each
+// use (the row loop's barriers keep the compiler from hoisting the reads)
+// keeps ~30 doubles out of the scalar register file.
+__device__ __forceinline__ void stage_hot(const Hot* __restrict__ src, Hot* dst) {
+  static_assert(sizeof(Hot) % 8 == 0, "Hot is copied as doubles");
+  constexpr int n = sizeof(Hot) / 8;
+  const double* s = reinterpret_cast<const double*>(src);
+  double* d = reinterpret_cast<double*>(dst);
+  for (int t = threadIdx.x; t < n; t += blockDim.x) d[t] = s[t];
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Plain kernel: one thread per node, every stencil point read from global
+// memory and its velocity recomputed. Reference for the fused kernel.
+// ---------------------------------------------------------------------------
+template <int VER>
+__global__ __launch_bounds__(256) void k_step_plain(Field F, const Hot* __restrict__ hot,
+                                                    const Cold* __restrict__ cold, int* flag) {
+  __shared__ Hot hs;
+  stage_hot(hot, &hs);
+  const Hot& c = hs;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  if (x >= F.nx || y >= F.ny) return;
+  if (is_wall_node(c, x, y, F.nx, F.ny)) return;
+  const Src cx = resolve(x, F.nx, c.bc[0], c.bc[1], 0);
+  const Src cy = resolve(y, F.ny, c.bc[2], c.bc[3], 2);
+  double f[16], fxp[16], fxm[16], fyp[16], fym[16];
+  load_point(F, cold, cx, cy, f);
+  load_point(F, cold, resolve(x + 1, F.nx, c.bc[0], c.bc[1], 0), cy, fxp);
+  load_point(F, cold, resolve(x - 1, F.nx, c.bc[0], c.bc[1], 0), cy, fxm);
+  load_point(F, cold, cx, resolve(y + 1, F.ny, c.bc[2], c.bc[3], 2), fyp);
+  load_point(F, cold, cx, resolve(y - 1, F.ny, c.bc[2], c.bc[3], 2), fym);
+  NbrVel nv;
+  velocity_of(fxp, nv.ux_xp, nv.uy_xp);
+  velocity_of(fxm, nv.ux_xm, nv.uy_xm);
+  velocity_of(fyp, nv.ux_yp, nv.uy_yp);
+  velocity_of(fym, nv.ux_ym, nv.uy_ym);
+  double out[16];
+  const bool ok = node_update<VER>(c, f, fxp, fxm, fyp, fym, nv, out);
+  if (!ok) flag[0] = 1;
+  store_node(F, x, y, out);
+  walls_from<VER>(F, c, cold, x, y, out);
+}
+
+// ---------------------------------------------------------------------------
+// Fused kernel. A workgroup of WAVES wavefronts owns a tile of STRIP columns
+// by `rows` rows and marches up it WAVES rows at a time. The 64 lanes of a
+// wave hold columns x0-1 .. x0+62; lanes 0 and 63 are halo lanes (ghosts at
+// the domain edge) that produce no output. Rows y-1 .. y+WAVES live in a
+// ring of RING rows in LDS (16 distributions + velocity per lane), so each
+// distribution is read from HBM about once; each wave prefetches its next
+// row into registers while it computes the current one.
+// ---------------------------------------------------------------------------
+constexpr int STRIP = 62;
+constexpr int WAVES = 4;
+constexpr int RING = WAVES + 2;
+constexpr int NV = 18;  // 16 distributions + u_x + u_y per ring entry
+
+// Convection of all 16 velocities with the stencil values read from the LDS
+// ring rows (current row r0, rows above/below rp/rm) as they are needed.
+template <int I>
+struct ConvLds {
+  __device__ __forceinline__ static void run(const Hot& c, const double (*r0)[64], const double (*rp)[64],
+                                             const double (*rm)[64], int lane, int lp, int lm, double* out) {
+    out[I] = convect<I>(c, r0[I][lane], VX[I] ? r0[I][lp] : 0.0, VX[I] ? r0[I][lm] : 0.0,
+                        VY[I] ? rp[I][lane] : 0.0, VY[I] ? rm[I][lane] : 0.0);
+    ConvLds<I + 1>::run(c, r0, rp, rm, lane, lp, lm, out);
+  }
+};
+template <>
+struct ConvLds<16> {
+  __device__ __forceinline__ static void run(const Hot&, const double (*)[64], const double (*)[64],
+                                             const double (*)[64], int, int, int, double*) {}
+};
+
+struct MarchGeom {
+  int nstrips;  // ceil(nx / STRIP)
+  int rows;     // rows per tile (multiple of WAVES)
+  int nsegs;    // ceil(ny / rows)
+  int ntiles;   // nstrips * nsegs
+  int per_xcd;  // ceil(ntiles / 8)
+};
+
+// Workgroups are dealt to the 8 XCDs round-robin; give each XCD a contiguous
+// run of tiles (x fastest) so tiles sharing halo rows and columns use the
+// same L2.
+__device__ __forceinline__ int xcd_tile(int b, const MarchGeom& g) { return (b % 8) * g.per_xcd + b / 8; }
+
+template <int VER, bool WALLS>
+__global__ __launch_bounds__(64 * WAVES, 2) void k_step_fused(Field F, const Hot* __restrict__ hot,
+                                                               const Cold* __restrict__ cold, MarchGeom g, int* flag) {
+  __shared__ double ring[RING][NV][64];
+  __shared__ Hot hs;
+  const int tile = xcd_tile(blockIdx.x, g);
+  if (tile >= g.ntiles) return;  // whole workgroup leaves together
+  stage_hot(hot, &hs);
+  const Hot& c = hs;
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int strip = tile % g.nstrips, seg = tile / g.nstrips;
+  const int x = strip * STRIP - 1 + lane;
+  const int y0 = seg * g.rows;
+  const int y1 = min(y0 + g.rows, F.ny);
+  // lanes right of the x = nx ghost lane idle on a valid column
+  const Src sx = (x <= F.nx) ? resolve(x, F.nx, c.bc[0], c.bc[1], 0) : Src{F.nx - 1, 0, -1};
+  const bool out_lane = lane >= 1 && lane <= STRIP && x < F.nx;
+  const int lm = lane > 0 ? lane - 1 : 0;
+  const int lp = lane < 63 ? lane + 1 : 63;
+  const int base = y0 - 1;  // row held in ring slot 0 at the start
+
+  // prologue: rows y0-1 .. y0+WAVES (only those <= y1 are ever read)
+  for (int r = w; r < RING; r += WAVES) {
+    const int yr = base + r;
+    if (yr <= y1) {
+      double f[16];
+      load_point(F, cold, sx, resolve(yr, F.ny, c.bc[2], c.bc[3], 2), f);
+      double ux, uy;
+      velocity_of(f, ux, uy);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) ring[r][i][lane] = f[i];
+      ring[r][16][lane] = ux;
+      ring[r][17][lane] = uy;
+    }
+  }
+
+  bool ok = true;
+  for (int Y = y0; Y < y1; Y += WAVES) {
+    // prefetch the row that replaces row Y-1+w in the ring
+    const int yn = Y + WAVES + 1 + w;
+    const bool have = yn <= y1;
+    double fn[16];
+    if (have) load_point(F, cold, sx, resolve(yn, F.ny, c.bc[2], c.bc[3], 2), fn);
+    __syncthreads();
+    const int y = Y + w;
+    if (y < y1 && out_lane && (!WALLS || !is_wall_node(c, x, y, F.nx, F.ny))) {
+      const int s0 = (y - base) % RING, sp = (y + 1 - base) % RING, sm = (y - 1 - base) % RING;
+      double out[16];
+      // convection first, reading each neighbour value from LDS as it is used
+      ConvLds<0>::run(c, ring[s0], ring[sp], ring[sm], lane, lp, lm, out);
+      double f[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) f[i] = ring[s0][i][lane];
+      NbrVel nv;
+      nv.ux_xp = ring[s0][16][lp];
+      nv.uy_xp = ring[s0][17][lp];
+      nv.ux_xm = ring[s0][16][lm];
+      nv.uy_xm = ring[s0][17][lm];
+      nv.ux_yp = ring[sp][16][lane];
+      nv.uy_yp = ring[sp][17][lane];
+      nv.ux_ym = ring[sm][16][lane];
+      nv.uy_ym = ring[sm][17][lane];
+      ok &= collide_add<VER>(c, f, nv, out);
+      store_node(F, x, y, out);
+      if (WALLS) walls_from<VER>(F, c, cold, x, y, out);
+    }
+    __syncthreads();
+    if (have) {
+      double ux, uy;
+      velocity_of(fn, ux, uy);
+      const int sn = (yn - base) % RING;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) ring[sn][i][lane] = fn[i];
+      ring[sn][16][lane] = ux;
+      ring[sn][17][lane] = uy;
+    }
+  }
+  if (!ok) flag[0] = 1;
+}
+
+// ---------------------------------------------------------------------------
+// Initial state and output moments.
+// ---------------------------------------------------------------------------
+template <int VER>
+__global__ void k_init(Field F, const double* __restrict__ rho, const double* __restrict__ ux,
+                       const double* __restrict__ uy, const double* __restrict__ T) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= F.nx) return;
+  const long long k = (long long)y * F.nx + x;
+  double f[16];
+  equilibrium_f<VER>(rho[k], ux[k], uy[k], T[k], f);
+  double* p = F.fout + (long long)y * F.pitch + x;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) p[i * F.plane] = f[i];
+}
+
+__global__ void k_moments(Field F, double* rho, double* ux, double* uy, double* T, double* P) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= F.nx) return;
+  const double* p = F.fin + (long long)y * F.pitch + x;
+  double f[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) f[i] = p[i * F.plane];
+  double m[16];
+  moments_from_f(f, m);
+  const double r = m[0], ir = 1.0 / r;
+  const double u = m[1] * ir, v = m[2] * ir;
+  const double t = m[3] * ir - 0.5 * (u * u + v * v);
+  const long long k = (long long)y * F.nx + x;
+  if (rho) rho[k] = r;
+  if (ux) ux[k] = u;
+  if (uy) uy[k] = v;
+  if (T) T[k] = t;
+  if (P) P[k] = r * t;
+}
+
+}  // namespace lbm

@@ -1,0 +1,142 @@
+// Device-side description of one time step and the node update shared by
+// every step kernel (plain, fused, batched). The update follows Eq. (3) with
+// the scheme of Sec. III: explicit collision at the old level plus per-axis
+// central Lax-Wendroff convection, and the energy-flux modification (Sec. II).
+#pragma once
+
+#include "lbm_node.h"
+
+namespace lbm {
+
+enum { BC_PERIODIC = 0, BC_ZERO_GRADIENT = 1, BC_SPECULAR = 2, BC_NEQ_WALL = 3, BC_DIRICHLET_EQ = 4 };
+
+// Per-problem coefficients read in the inner loop (kept small: they live in
+// scalar registers).
+struct Hot {
+  double cq[12];   // -dt s_k for k = 5..16 (index k-5)
+  double cmod[4];  // -dt (s7/s5-1), -dt (s7/s6-1), -dt (s8/s6-1), -dt sgn (s8/s5-1); 0 if unmodified
+  double inv2dx, inv2dy;
+  // Lax-Wendroff along one axis for a velocity component v = +1 / +2 with
+  // c = v dt/dx: coefficient of f(x+1) is p = (c^2 - c)/2 and of f(x-1) is
+  // m = (c^2 + c)/2; for v = -1 / -2 the two swap. Stored as p1, m1, p2, m2.
+  double lx[4], ly[4];
+  // centre coefficient 1 - cx^2 - cy^2 for (|vx|, |vy|) = (1,0), (0,1), (1,1), (2,0), (0,2), (2,2)
+  double c0[6];
+  int bc[4];
+  int version;
+  int modified;
+};
+
+// Rarely read per-problem data.
+struct Cold {
+  double ghost[4][16];  // equilibrium ghosts of DIRICHLET_EQ sides
+  double wall[4][4];    // (rho, ux, uy, T) per side for NEQ walls
+};
+
+// Neighbour velocities the modification needs.
+struct NbrVel {
+  double ux_xp, uy_xp, ux_xm, uy_xm;  // at x+1, x-1
+  double ux_yp, uy_yp, ux_ym, uy_ym;  // at y+1, y-1
+};
+
+LBM_HD constexpr int c0_index(int i) {
+  return (VX[i] != 0 && VY[i] == 0) ? (VX[i] == 1 || VX[i] == -1 ? 0 : 3)
+         : (VX[i] == 0)             ? (VY[i] == 1 || VY[i] == -1 ? 1 : 4)
+         : (VX[i] == 1 || VX[i] == -1) ? 2
+                                       : 5;
+}
+
+LBM_HD void velocity_of(const double* f, double& ux, double& uy) {
+  double rho, jx, jy;
+  density_momentum(f, rho, jx, jy);
+  const double ir = 1.0 / rho;
+  ux = jx * ir;
+  uy = jy * ir;
+}
+
+// Lax-Wendroff convection of velocity i plus the centre term:
+// lwc f + sum over axes of (p f(+1) + m f(-1)).
+template <int I>
+LBM_HD double convect(const Hot& c, double f, double fxp, double fxm, double fyp, double fym) {
+  double v = c.c0[c0_index(I)] * f;
+  if (VX[I] == 1) v += c.lx[0] * fxp + c.lx[1] * fxm;
+  if (VX[I] == -1) v += c.lx[1] * fxp + c.lx[0] * fxm;
+  if (VX[I] == 2) v += c.lx[2] * fxp + c.lx[3] * fxm;
+  if (VX[I] == -2) v += c.lx[3] * fxp + c.lx[2] * fxm;
+  if (VY[I] == 1) v += c.ly[0] * fyp + c.ly[1] * fym;
+  if (VY[I] == -1) v += c.ly[1] * fyp + c.ly[0] * fym;
+  if (VY[I] == 2) v += c.ly[2] * fyp + c.ly[3] * fym;
+  if (VY[I] == -2) v += c.ly[3] * fyp + c.ly[2] * fym;
+  return v;
+}
+
+template <int I>
+struct ConvAll {
+  LBM_HD static void run(const Hot& c, const double* f, const double* fxp, const double* fxm, const double* fyp,
+                         const double* fym, double* out) {
+    out[I] = convect<I>(c, f[I], fxp[I], fxm[I], fyp[I], fym[I]);
+    ConvAll<I + 1>::run(c, f, fxp, fxm, fyp, fym, out);
+  }
+};
+template <>
+struct ConvAll<16> {
+  LBM_HD static void run(const Hot&, const double*, const double*, const double*, const double*, const double*,
+                         double*) {}
+};
+
+// Collision of one node in velocity space, -dt M^-1 Q (Sec. II), added to
+// `acc`. Returns false when rho <= 0, T <= 0 or a NaN appears.
+template <int VER>
+LBM_HD bool collide_add(const Hot& c, const double* f, const NbrVel& nv, double* acc) {
+  double m[16];
+  moments_from_f(f, m);
+  const double rho = m[0], jx = m[1], jy = m[2], e = m[3];
+  double q[16];
+  equilibrium_moments<VER>(rho, jx, jy, e, q);
+  double col[16];
+#pragma unroll
+  for (int k = 4; k < 16; ++k) col[k] = c.cq[k - 4] * (m[k] - q[k]);
+  const double ir = 1.0 / rho;
+  const double ux = jx * ir, uy = jy * ir;
+  const double T = e * ir - 0.5 * (ux * ux + uy * uy);
+  {
+    // energy-flux modification; its coefficients are exactly 0 for the
+    // unmodified model, so the terms then add exactly 0 (no branch)
+    const double A = (nv.ux_xp - nv.ux_xm) * c.inv2dx - (nv.uy_yp - nv.uy_ym) * c.inv2dy;
+    const double B = (nv.uy_xp - nv.uy_xm) * c.inv2dx + (nv.ux_yp - nv.ux_ym) * c.inv2dy;
+    const double rT = rho * T;
+    col[6] += c.cmod[0] * rT * ux * A + c.cmod[1] * rT * uy * B;
+    col[7] += c.cmod[2] * rT * ux * B + c.cmod[3] * rT * uy * A;
+  }
+  double df[16];
+  f_from_nonconserved(col, df);
+#pragma unroll
+  for (int i = 0; i < 16; ++i) acc[i] += df[i];
+  return (rho > 0.0) && (T > 0.0);
+}
+
+// New distributions at one interior node.
+template <int VER>
+LBM_HD bool node_update(const Hot& c, const double* f, const double* fxp, const double* fxm, const double* fyp,
+                        const double* fym, const NbrVel& nv, double* out) {
+  ConvAll<0>::run(c, f, fxp, fxm, fyp, fym, out);
+  return collide_add<VER>(c, f, nv, out);
+}
+
+// Non-equilibrium extrapolation wall node from its fluid neighbour's new
+// distributions fn (Sec. IV.A): f_w = f^eq(rho_n, u_w, T_w) + (f_n - f^eq(rho_n, u_n, T_n)).
+template <int VER>
+LBM_HD void neq_wall(const double* wall, const double* fn, double* fw) {
+  double m[16];
+  moments_from_f(fn, m);
+  const double rho = m[0], ir = 1.0 / rho;
+  const double ux = m[1] * ir, uy = m[2] * ir;
+  const double T = m[3] * ir - 0.5 * (ux * ux + uy * uy);
+  double ew[16], en[16];
+  equilibrium_f<VER>(rho, wall[1], wall[2], wall[3], ew);
+  equilibrium_f<VER>(rho, ux, uy, T, en);
+#pragma unroll
+  for (int i = 0; i < 16; ++i) fw[i] = ew[i] + (fn[i] - en[i]);
+}
+
+}  // namespace lbm

@@ -1,0 +1,150 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle on the
+paper-shaped workloads, plus edge cases. Tolerance: 1e-11 per moment field
+(definition in gpu_util)."""
+
+import numpy as np
+import pytest
+
+from gpu_util import assert_parity, gpu_run, log, oracle_run
+from paper_1106_0785_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("Pr", [0.5, 1.0, 2.0])
+def test_couette_full_run(Pr):
+    """Thermal Couette 4 x 64, walls on the first/last row, 20000 steps."""
+    p, fl, _ = inputs.couette(Pr)
+    log("couette Pr=%g 4x64 20000 steps" % Pr)
+    g, gf = gpu_run(p, fl, 20000)
+    o, _ = oracle_run(p, fl, 20000)
+    assert_parity(g, o, what="couette Pr=%g" % Pr)
+
+
+@pytest.mark.parametrize("kind,steps", [("sod", 20000), ("lax", 14000)])
+def test_riemann_full_run(kind, steps):
+    """2000 x 4 Riemann problems for their full run; the oracle runs the
+    y-uniform problem on one row (its rows are bitwise equal, pinned on CPU)."""
+    p, fl, _ = inputs.riemann(kind, Pr=1.0, nx=2000, ny=4)
+    log("riemann %s 2000x4 %d steps" % (kind, steps))
+    g, _ = gpu_run(p, fl, steps)
+    p1, fl1, _ = inputs.riemann(kind, Pr=1.0, nx=2000, ny=1)
+    o, _ = oracle_run(p1, fl1, steps)
+    for j in range(4):
+        gj = {k: v[j:j + 1] for k, v in g.items()}
+        assert_parity(gj, o, what="riemann %s row %d" % (kind, j))
+
+
+def test_rm_small_ragged():
+    p, fl, _ = inputs.rm(seed=4, nx=200, ny=42)
+    log("rm 200x42 300 steps")
+    g, _ = gpu_run(p, fl, 300)
+    o, _ = oracle_run(p, fl, 300)
+    assert_parity(g, o, what="rm 200x42")
+
+
+def test_rm_full_size_short_run():
+    p, fl, _ = inputs.rm(seed=0, nx=1024, ny=256)
+    log("rm 1024x256 60 steps")
+    g, _ = gpu_run(p, fl, 60)
+    o, _ = oracle_run(p, fl, 60)
+    assert_parity(g, o, what="rm 1024x256")
+
+
+def test_fused_equals_plain_kernel_bitwise():
+    p, fl, _ = inputs.rm(seed=2, nx=300, ny=100)
+    log("fused vs plain 300x100 50 steps")
+    _, f0 = gpu_run(p, fl, 50, variant=0)
+    _, f1 = gpu_run(p, fl, 50, variant=1)
+    assert np.array_equal(f0, f1)
+
+
+@pytest.mark.parametrize("rows", [4, 8, 16, 64])
+def test_tile_rows_do_not_change_result(rows):
+    p, fl, _ = inputs.rm(seed=3, nx=190, ny=77)
+    log("tile rows %d 190x77" % rows)
+    _, f = gpu_run(p, fl, 30, rows=rows)
+    _, ref = gpu_run(p, fl, 30, variant=1)
+    assert np.array_equal(f, ref)
+
+
+def _small(seed, nx, ny, bc, **kw):
+    p, fl = inputs.smooth_periodic(seed=seed, nx=nx, ny=ny, amp=0.06, **kw)
+    p["bc"] = bc
+    return p, fl
+
+
+CASES = {
+    "zero_gradient_x_specular_y": (["zero_gradient", "zero_gradient", "specular", "specular"], {}),
+    "specular_x_periodic_y": (["specular", "specular", "periodic", "periodic"], {}),
+    "periodic_both_v2": (["periodic"] * 4, {"eq_version": 2}),
+    "periodic_both_v3": (["periodic"] * 4, {"eq_version": 3}),
+    "unmodified": (["periodic"] * 4, {"modified": 0}),
+    "printed_q8_sign": (["periodic"] * 4, {"modified": 2}),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_boundary_and_model_variants(name):
+    bc, kw = CASES[name]
+    p, fl = _small(7, 70, 23, bc, **kw)
+    log("variant %s 70x23 200 steps" % name)
+    g, _ = gpu_run(p, fl, 200)
+    o, _ = oracle_run(p, fl, 200)
+    assert_parity(g, o, what=name)
+
+
+def test_dirichlet_ghost():
+    p, fl = _small(8, 66, 9, ["dirichlet_eq", "zero_gradient", "periodic", "periodic"])
+    p["wall"][0] = [1.05, 0.02, 0.0, 1.02]
+    log("dirichlet x_lo 66x9 200 steps")
+    g, _ = gpu_run(p, fl, 200)
+    o, _ = oracle_run(p, fl, 200)
+    assert_parity(g, o, what="dirichlet")
+
+
+def test_neq_walls_on_x():
+    p, fl, _ = inputs.couette_x(2.0, nx=40, ny=3)
+    log("neq walls on x 40x3 2000 steps")
+    g, _ = gpu_run(p, fl, 2000)
+    o, _ = oracle_run(p, fl, 2000)
+    assert_parity(g, o, what="neq x walls")
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (2, 2), (1, 37), (300, 1), (63, 5), (125, 3)])
+def test_degenerate_shapes(shape):
+    nx, ny = shape
+    p, fl = _small(5, nx, ny, ["periodic"] * 4)
+    log("shape %dx%d" % shape)
+    g, _ = gpu_run(p, fl, 100)
+    o, _ = oracle_run(p, fl, 100)
+    assert_parity(g, o, what="shape %dx%d" % shape)
+
+
+def test_couette_column_nx1():
+    p, fl, _ = inputs.couette(0.7, nx=1, ny=50)
+    g, _ = gpu_run(p, fl, 3000)
+    o, _ = oracle_run(p, fl, 3000)
+    assert_parity(g, o, what="couette nx=1")
+
+
+def test_zero_steps_returns_initial_state():
+    p, fl, _ = inputs.rm(seed=5, nx=64, ny=16)
+    g, _ = gpu_run(p, fl, 0)
+    o, _ = oracle_run(p, fl, 0)
+    assert_parity(g, o, tol=1e-14, what="zero steps")
+
+
+def test_health_flag_reports_blow_up():
+    """A sharp (unsmoothed) jump with the central stencil overflows within a
+    few hundred steps; lbm_check reports it."""
+    from paper_1106_0785_amd import lbm
+
+    p, fl, _ = inputs.riemann("sod", Pr=1.0, nx=400, ny=1, width_cells=1e-3)
+    sim = lbm.Simulation(p)
+    sim.init(**fl)
+    sim.step(3000)
+    with pytest.raises(lbm.LbmError) as e:
+        sim.check()
+    assert e.value.status == -5
+    sim.close()
