@@ -152,12 +152,25 @@ struct Macro {
   R rho, jx, jy, e, ux, uy, T;
 };
 
+// Order in which the dense sums below run over their index. The default
+// build sums in index order; ORACLE_REVERSED_SUMS builds the same arithmetic
+// with every dense sum taken in reverse order: an equally valid evaluation
+// of the same definition, used to measure a problem's FP64 noise floor.
+#ifdef ORACLE_REVERSED_SUMS
+inline int sum_index(int j) { return NQ - 1 - j; }
+#else
+inline int sum_index(int j) { return j; }
+#endif
+
 // f^ = M f, dense.
 template <class R>
 void to_moments(const R* f, R* fh) {
   for (int k = 0; k < NQ; ++k) {
     R acc = R(0);
-    for (int i = 0; i < NQ; ++i) acc += MROWS[k][i] * f[i];
+    for (int j = 0; j < NQ; ++j) {
+      const int i = sum_index(j);
+      acc += MROWS[k][i] * f[i];
+    }
     fh[k] = acc;
   }
 }
@@ -238,7 +251,10 @@ void feq_distribution(int version, R rho, R ux, R uy, R T, R* f) {
   feq_moments(version, m, q);
   for (int i = 0; i < NQ; ++i) {
     R acc = R(0);
-    for (int k = 0; k < NQ; ++k) acc += MINV[i][k] * q[k];
+    for (int j = 0; j < NQ; ++j) {
+      const int k = sum_index(j);
+      acc += MINV[i][k] * q[k];
+    }
     f[i] = acc;
   }
 }
@@ -351,7 +367,10 @@ void update_node(const oracle_params& p, const R* s, const Grid<R>& g, int x, in
   // Collision in velocity space: -dt M^-1 Q.
   for (int i = 0; i < NQ; ++i) {
     R coll = R(0);
-    for (int k = 0; k < NQ; ++k) coll += MINV[i][k] * Q[k];
+    for (int j = 0; j < NQ; ++j) {
+      const int k = sum_index(j);
+      coll += MINV[i][k] * Q[k];
+    }
     coll = -p.dt * coll;
 
     // Central Lax-Wendroff convection, axis by axis, as in G_ij (Sec. III).

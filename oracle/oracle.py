@@ -13,6 +13,13 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lbm_oracle.cpp")
 _LIB = os.path.join(_HERE, "liblbm_oracle.so")
+# The same source built with fused multiply-adds: a second rounding of the
+# same arithmetic, used only to measure how strongly a problem amplifies
+# rounding differences (the noise floor of any parity comparison).
+_LIB_FMA = os.path.join(_HERE, "liblbm_oracle_fma.so")
+# ... and with every dense sum taken in reverse index order.
+_LIB_REV = os.path.join(_HERE, "liblbm_oracle_rev.so")
+_VARIANTS = {"plain": _LIB, "fma": _LIB_FMA, "reversed": _LIB_REV}
 
 BC_CODES = {"periodic": 0, "zero_gradient": 1, "specular": 2, "neq_wall": 3, "dirichlet_eq": 4}
 
@@ -54,23 +61,24 @@ def lib_path():
 
 
 def build(force=False):
-    """Compile the oracle with g++ (plain -O2, OpenMP over nodes)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
-        cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared", _SRC, "-o", tmp]
-        subprocess.check_call(cmd)
-        os.replace(tmp, _LIB)
+    """Compile the oracle with g++ (plain -O2, OpenMP over nodes), and the
+    fused-multiply-add build of the same source."""
+    for path, extra in ((_LIB, []), (_LIB_FMA, ["-mfma", "-ffp-contract=fast"]), (_LIB_REV, ["-DORACLE_REVERSED_SUMS"])):
+        if force or not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+            tmp = path + ".tmp"
+            cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared"] + extra + [_SRC, "-o", tmp]
+            subprocess.check_call(cmd)
+            os.replace(tmp, path)
     return _LIB
 
 
-_lib = None
+_libs = {}
 
 
-def _load():
-    global _lib
-    if _lib is None:
+def _load(variant="plain"):
+    if variant not in _libs:
         build()
-        lib = ctypes.CDLL(_LIB)
+        lib = ctypes.CDLL(_VARIANTS[variant])
         P = ctypes.POINTER(ctypes.c_double)
         pp = ctypes.POINTER(OracleParams)
         lib.oracle_matrices.argtypes = [P, P, P]
@@ -82,8 +90,8 @@ def _load():
         lib.oracle_run_complex.argtypes = [pp, P, P, P, ctypes.c_int64, P, P, ctypes.c_int]
         lib.oracle_moments_complex.argtypes = [pp, P, P] + [P] * 8
         lib.oracle_max_threads.argtypes = []
-        _lib = lib
-    return _lib
+        _libs[variant] = lib
+    return _libs[variant]
 
 
 def _ptr(a):
@@ -145,12 +153,15 @@ def moments(p, f):
     return out
 
 
-def run(p, f, nsteps, nthreads=None):
+def run(p, f, nsteps, nthreads=None, variant="plain"):
+    """variant "fma" / "reversed": the same arithmetic rounded differently
+    (fused multiply-adds / dense sums in reverse order), to measure how far
+    FP64 rounding alone moves a problem's result."""
     p = _params(p)
     f = _f64(f)
     out = np.empty_like(f)
     nt = max_threads() if nthreads is None else int(nthreads)
-    if _load().oracle_run(ctypes.byref(p), _ptr(f), int(nsteps), _ptr(out), nt):
+    if _load(variant).oracle_run(ctypes.byref(p), _ptr(f), int(nsteps), _ptr(out), nt):
         raise ValueError("oracle_run rejected its arguments")
     return out
 

@@ -103,11 +103,6 @@ void make_coef(const lbm_params* p, Hot* c, Cold* cold) {
     c->ly[2 * (v - 1)] = 0.5 * cy * cy - 0.5 * cy;
     c->ly[2 * (v - 1) + 1] = 0.5 * cy * cy + 0.5 * cy;
   }
-  const int ax[6] = {1, 0, 1, 2, 0, 2}, ay[6] = {0, 1, 1, 0, 2, 2};
-  for (int j = 0; j < 6; ++j) {
-    const double cx = ax[j] * rx, cy = ay[j] * ry;
-    c->c0[j] = 1.0 - cx * cx - cy * cy;
-  }
   for (int sd = 0; sd < 4; ++sd) {
     for (int j = 0; j < 4; ++j) cold->wall[sd][j] = p->wall[sd][j];
     if (p->bc[sd] == LBM_BC_DIRICHLET_EQ)
@@ -116,6 +111,27 @@ void make_coef(const lbm_params* p, Hot* c, Cold* cold) {
   }
   c->version = p->eq_version;
   c->modified = p->modified;
+}
+
+__global__ void k_moments(Field F, double* rho, double* ux, double* uy, double* T, double* P) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= F.nx) return;
+  const double* p = F.fin + (long long)y * F.pitch + x;
+  double f[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) f[i] = p[i * F.plane];
+  double m[16];
+  moments_from_f(f, m);
+  const double r = m[0], ir = 1.0 / r;
+  const double u = m[1] * ir, v = m[2] * ir;
+  const double t = m[3] * ir - 0.5 * (u * u + v * v);
+  const long long k = (long long)y * F.nx + x;
+  if (rho) rho[k] = r;
+  if (ux) ux[k] = u;
+  if (uy) uy[k] = v;
+  if (T) T[k] = t;
+  if (P) P[k] = r * t;
 }
 
 MarchGeom march_geom(int nx, int ny, int rows) {

@@ -20,8 +20,6 @@ struct Hot {
   // c = v dt/dx: coefficient of f(x+1) is p = (c^2 - c)/2 and of f(x-1) is
   // m = (c^2 + c)/2; for v = -1 / -2 the two swap. Stored as p1, m1, p2, m2.
   double lx[4], ly[4];
-  // centre coefficient 1 - cx^2 - cy^2 for (|vx|, |vy|) = (1,0), (0,1), (1,1), (2,0), (0,2), (2,2)
-  double c0[6];
   int bc[4];
   int version;
   int modified;
@@ -39,13 +37,6 @@ struct NbrVel {
   double ux_yp, uy_yp, ux_ym, uy_ym;  // at y+1, y-1
 };
 
-LBM_HD constexpr int c0_index(int i) {
-  return (VX[i] != 0 && VY[i] == 0) ? (VX[i] == 1 || VX[i] == -1 ? 0 : 3)
-         : (VX[i] == 0)             ? (VY[i] == 1 || VY[i] == -1 ? 1 : 4)
-         : (VX[i] == 1 || VX[i] == -1) ? 2
-                                       : 5;
-}
-
 LBM_HD void velocity_of(const double* f, double& ux, double& uy) {
   double rho, jx, jy;
   density_momentum(f, rho, jx, jy);
@@ -54,19 +45,23 @@ LBM_HD void velocity_of(const double* f, double& ux, double& uy) {
   uy = jy * ir;
 }
 
-// Lax-Wendroff convection of velocity i plus the centre term:
-// lwc f + sum over axes of (p f(+1) + m f(-1)).
+// Lax-Wendroff convection increment of velocity I (Sec. III, G_ij):
+// sum over axes of p (f(+1) - f) + m (f(-1) - f), with p = (c^2 - c)/2 and
+// m = (c^2 + c)/2 for c = v dt/dx. Written with differences so that a
+// uniform state is reproduced exactly and the grid totals of rho, j, e are
+// conserved to rounding (a centre coefficient 1 - c^2 would scale every
+// distribution by a rounding bias each step).
 template <int I>
 LBM_HD double convect(const Hot& c, double f, double fxp, double fxm, double fyp, double fym) {
-  double v = c.c0[c0_index(I)] * f;
-  if (VX[I] == 1) v += c.lx[0] * fxp + c.lx[1] * fxm;
-  if (VX[I] == -1) v += c.lx[1] * fxp + c.lx[0] * fxm;
-  if (VX[I] == 2) v += c.lx[2] * fxp + c.lx[3] * fxm;
-  if (VX[I] == -2) v += c.lx[3] * fxp + c.lx[2] * fxm;
-  if (VY[I] == 1) v += c.ly[0] * fyp + c.ly[1] * fym;
-  if (VY[I] == -1) v += c.ly[1] * fyp + c.ly[0] * fym;
-  if (VY[I] == 2) v += c.ly[2] * fyp + c.ly[3] * fym;
-  if (VY[I] == -2) v += c.ly[3] * fyp + c.ly[2] * fym;
+  double v = 0.0;
+  if (VX[I] == 1) v += c.lx[0] * (fxp - f) + c.lx[1] * (fxm - f);
+  if (VX[I] == -1) v += c.lx[1] * (fxp - f) + c.lx[0] * (fxm - f);
+  if (VX[I] == 2) v += c.lx[2] * (fxp - f) + c.lx[3] * (fxm - f);
+  if (VX[I] == -2) v += c.lx[3] * (fxp - f) + c.lx[2] * (fxm - f);
+  if (VY[I] == 1) v += c.ly[0] * (fyp - f) + c.ly[1] * (fym - f);
+  if (VY[I] == -1) v += c.ly[1] * (fyp - f) + c.ly[0] * (fym - f);
+  if (VY[I] == 2) v += c.ly[2] * (fyp - f) + c.ly[3] * (fym - f);
+  if (VY[I] == -2) v += c.ly[3] * (fyp - f) + c.ly[2] * (fym - f);
   return v;
 }
 
@@ -85,6 +80,7 @@ struct ConvAll<16> {
 };
 
 // Collision of one node in velocity space, -dt M^-1 Q (Sec. II), added to
+// the increments `acc`, then the new distributions f + acc are written to
 // `acc`. Returns false when rho <= 0, T <= 0 or a NaN appears.
 template <int VER>
 LBM_HD bool collide_add(const Hot& c, const double* f, const NbrVel& nv, double* acc) {
@@ -111,7 +107,7 @@ LBM_HD bool collide_add(const Hot& c, const double* f, const NbrVel& nv, double*
   double df[16];
   f_from_nonconserved(col, df);
 #pragma unroll
-  for (int i = 0; i < 16; ++i) acc[i] += df[i];
+  for (int i = 0; i < 16; ++i) acc[i] = f[i] + (acc[i] + df[i]);
   return (rho > 0.0) && (T > 0.0);
 }
 

@@ -149,7 +149,7 @@ def post_shock(mach, rho1=1.0, p1=1.0, u1=0.0, gamma=GAMMA):
 # --------------------------------------------------------------------------
 def rm(seed=0, nx=1024, ny=256, dx=0.003, dt=1e-5, Pr=0.71, s5=1e4, s_other=1e5, mach=None,
        heavy=3.0, amp_frac=0.05, max_modes=4, width_cells=3.0, shock_gap_cells=20, modified=1,
-       interface_offset=None):
+       interface_offset=None, wall_ramp_cells=12.0):
     """Returns (params, fields, meta). meta['a'] is the per-row interface
     displacement field a(y) (in units of dy) that shapes the interface; the
     initial fields are smooth functions of it."""
@@ -174,14 +174,18 @@ def rm(seed=0, nx=1024, ny=256, dx=0.003, dt=1e-5, Pr=0.71, s5=1e4, s_other=1e5,
     x0_cells = 0.35 * nx
     meta["x0_cells"] = x0_cells
     meta["shock_cells"] = x0_cells - np.max(np.abs(a_cells)) - shock_gap_cells
-    fields = rm_fields(nx, ny, a_cells, mach, heavy, x0_cells, meta["shock_cells"], width_cells)
+    meta["wall_ramp_cells"] = wall_ramp_cells
+    fields = rm_fields(nx, ny, a_cells, mach, heavy, x0_cells, meta["shock_cells"], width_cells, wall_ramp_cells)
     return p, fields, meta
 
 
-def rm_fields(nx, ny, a_cells, mach, heavy, x0_cells, shock_cells, width_cells, xp=np):
+def rm_fields(nx, ny, a_cells, mach, heavy, x0_cells, shock_cells, width_cells, wall_ramp_cells=12.0, xp=np):
     """Initial fields of the shock/interface problem as smooth functions of the
     per-row interface displacement a (cells). `xp` may be numpy or torch; with
-    complex or differentiable a the fields carry the perturbation."""
+    complex or differentiable a the fields carry the perturbation. The driver
+    gas behind the shock is brought smoothly to rest at the reflecting left
+    wall (a sharp velocity jump against the mirror ghost would excite
+    grid-scale oscillations of the central stencil)."""
     rho2, du, p2, _ = post_shock(mach)
     i = xp.arange(nx) + 0.5
     if xp is np:
@@ -192,8 +196,9 @@ def rm_fields(nx, ny, a_cells, mach, heavy, x0_cells, shock_cells, width_cells, 
         aa = a_cells[:, None]
     w_int = 0.5 * (1.0 + xp.tanh((ii - x0_cells - aa) / width_cells))    # 0 light -> 1 heavy
     w_sh = 0.5 * (1.0 + xp.tanh((ii - shock_cells) / width_cells)) + 0 * aa  # 0 shocked -> 1 quiet
+    ramp = xp.tanh(ii / wall_ramp_cells) + 0 * aa
     rho_light = rho2 + (1.0 - rho2) * w_sh
-    u_light = du * (1.0 - w_sh)
+    u_light = du * (1.0 - w_sh) * ramp
     p_light = p2 + (1.0 - p2) * w_sh
     rho = rho_light + (heavy - rho_light) * w_int
     ux = u_light * (1.0 - w_int)

@@ -51,21 +51,60 @@ def test_rm_full_size_short_run():
     assert_parity(g, o, what="rm 1024x256")
 
 
-def test_fused_equals_plain_kernel_bitwise():
+def _kernel_diff(a, b):
+    return float(np.max(np.abs(a - b) / np.abs(b).max(axis=(1, 2), keepdims=True)))
+
+
+def test_fused_matches_plain_kernel():
+    """Same node arithmetic, different data movement: the results agree to
+    a few ulps (the compiler may contract multiply-adds differently)."""
     p, fl, _ = inputs.rm(seed=2, nx=300, ny=100)
-    log("fused vs plain 300x100 50 steps")
     _, f0 = gpu_run(p, fl, 50, variant=0)
     _, f1 = gpu_run(p, fl, 50, variant=1)
-    assert np.array_equal(f0, f1)
+    d = _kernel_diff(f0, f1)
+    log("fused vs plain 300x100 50 steps: max diff %.2e (bitwise equal: %s)" % (d, np.array_equal(f0, f1)))
+    assert d <= 1e-13
 
 
 @pytest.mark.parametrize("rows", [4, 8, 16, 64])
 def test_tile_rows_do_not_change_result(rows):
+    """Tile height changes only which workgroup computes a node: bitwise equal."""
     p, fl, _ = inputs.rm(seed=3, nx=190, ny=77)
-    log("tile rows %d 190x77" % rows)
     _, f = gpu_run(p, fl, 30, rows=rows)
-    _, ref = gpu_run(p, fl, 30, variant=1)
+    _, ref = gpu_run(p, fl, 30, rows=4)
+    log("tile rows %d 190x77: bitwise equal to rows 4: %s" % (rows, np.array_equal(f, ref)))
     assert np.array_equal(f, ref)
+
+
+def test_conservation_periodic():
+    """Totals of rho, j, e on a periodic grid are conserved to rounding."""
+    from paper_1106_0785_amd import lbm
+
+    p, fl = inputs.smooth_periodic(seed=11, nx=200, ny=120, amp=0.08)
+    sim = lbm.Simulation(p)
+    sim.init(**fl)
+
+    def totals():
+        m = {k: v.cpu().numpy() for k, v in sim.moments().items()}
+        r, u, v, T = m["rho"], m["ux"], m["uy"], m["T"]
+        return np.array([r.sum(), (r * u).sum(), (r * v).sum(), (r * (T + 0.5 * (u * u + v * v))).sum()])
+
+    t0 = totals()
+    sim.step(1000)
+    t1 = totals()
+    sim.check()
+    sim.close()
+    rel = np.abs(t1 - t0) / np.abs(t0)
+    log("conservation 200x120 1000 steps: relative drift %s" % rel)
+    assert np.all(rel <= 1e-13)
+
+
+def test_rm_5000_steps_reduced_grid():
+    """The shock/interface problem for its full 5000 steps on a 256 x 64 grid."""
+    p, fl, _ = inputs.rm(seed=6, nx=256, ny=64)
+    g, _ = gpu_run(p, fl, 5000)
+    o, _ = oracle_run(p, fl, 5000)
+    assert_parity(g, o, what="rm 256x64 5000 steps")
 
 
 def _small(seed, nx, ny, bc, **kw):
