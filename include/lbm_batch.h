@@ -1,0 +1,80 @@
+/*
+ * liblbm batched form: many independent one-dimensional problems of uneven
+ * length and parameters advanced together (Riemann lines along x with
+ * ny = 1, thermal Couette columns along y with nx = 1; Sec. IV of the paper
+ * for the problems, Sec. II-III for the step). Conventions as in lbm.h.
+ *
+ * Layout: instance i owns nodes [lbm_batch_offset(b, i), lbm_batch_offset(b,
+ * i + 1)) of every concatenated field array (its own [ny][nx] order), and
+ * 16 * (its node count) entries of a concatenated distribution array
+ * ([16][N_i] per instance, instances back to back).
+ *
+ * Execution: a workgroup owns one chunk of one instance plus a halo of h
+ * nodes, advances it h steps in LDS and writes the chunk back; one call of
+ * lbm_batch_step(b, K) is ceil(K/h) such launches over every chunk of every
+ * instance, captured once in a hipGraph and replayed on later calls with the
+ * same K. Results equal those of lbm_step on each instance alone.
+ */
+#ifndef LBM_BATCH_H_
+#define LBM_BATCH_H_
+
+#include "lbm.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_batch lbm_batch;
+
+/* Device workspace for n instances (two arenas, a backup arena used by the
+ * tuner, descriptors, chunk list, budgets, status); 0 if any instance is
+ * invalid (lbm_create's rules), is not one-dimensional (nx == 1 or ny == 1),
+ * or is a periodic line longer than 128 nodes. */
+size_t lbm_batch_workspace_bytes(const lbm_params* inst, int32_t n);
+
+/* Binds a batch to caller-owned workspace and stream (as lbm_create). */
+lbm_status lbm_batch_create(const lbm_params* inst, int32_t n, void* d_workspace, size_t ws_bytes, void* hip_stream,
+                            lbm_batch** out);
+
+/* First node of instance i in concatenated field arrays; i == n gives the
+ * total node count; -1 if out of range. */
+int64_t lbm_batch_offset(const lbm_batch* b, int32_t i);
+
+/* f = M^-1 f^eq(rho, u, T) for every instance (Sec. II, Eqs. 14a-14i);
+ * concatenated device field arrays. */
+lbm_status lbm_batch_init(lbm_batch* b, const double* d_rho, const double* d_ux, const double* d_uy,
+                          const double* d_T);
+
+/* Optional per-instance step budgets (host array of n, NULL = no limit):
+ * during one lbm_batch_step(b, K) instance i advances min(K, steps[i]) steps. */
+lbm_status lbm_batch_set_budgets(lbm_batch* b, const int64_t* steps);
+
+/* Advances every instance nsteps time steps (Eq. 3, scheme of Sec. III). */
+lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps);
+
+/* rho, u_x, u_y, T, p of every instance, concatenated (any may be NULL). */
+lbm_status lbm_batch_moments(lbm_batch* b, double* d_rho, double* d_ux, double* d_uy, double* d_T, double* d_p);
+
+/* Current distributions, [16][N_i] per instance, concatenated. */
+lbm_status lbm_batch_get_f(lbm_batch* b, double* d_f);
+
+/* Schedule: region = nodes per workgroup (128 or 256), steps_per_launch = h
+ * (region - 2 h >= 32), use_graph = capture lbm_batch_step in a hipGraph. */
+lbm_status lbm_batch_set_schedule(lbm_batch* b, int32_t region, int32_t steps_per_launch, int32_t use_graph);
+lbm_status lbm_batch_get_schedule(const lbm_batch* b, int32_t* region, int32_t* steps_per_launch, int32_t* nchunks);
+
+/* Autotuner: times every admissible (region, h) for probe_steps steps on the
+ * current state (synchronising the stream), restores the state and keeps the
+ * fastest schedule; *best_ms receives its time. */
+lbm_status lbm_batch_tune(lbm_batch* b, int64_t probe_steps, double* best_ms);
+
+/* As lbm_check, for the batch. */
+lbm_status lbm_batch_check(lbm_batch* b);
+
+void lbm_batch_destroy(lbm_batch* b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_BATCH_H_ */

@@ -113,27 +113,6 @@ void make_coef(const lbm_params* p, Hot* c, Cold* cold) {
   c->modified = p->modified;
 }
 
-__global__ void k_moments(Field F, double* rho, double* ux, double* uy, double* T, double* P) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y;
-  if (x >= F.nx) return;
-  const double* p = F.fin + (long long)y * F.pitch + x;
-  double f[16];
-#pragma unroll
-  for (int i = 0; i < 16; ++i) f[i] = p[i * F.plane];
-  double m[16];
-  moments_from_f(f, m);
-  const double r = m[0], ir = 1.0 / r;
-  const double u = m[1] * ir, v = m[2] * ir;
-  const double t = m[3] * ir - 0.5 * (u * u + v * v);
-  const long long k = (long long)y * F.nx + x;
-  if (rho) rho[k] = r;
-  if (ux) ux[k] = u;
-  if (uy) uy[k] = v;
-  if (T) T[k] = t;
-  if (P) P[k] = r * t;
-}
-
 MarchGeom march_geom(int nx, int ny, int rows) {
   MarchGeom g;
   g.nstrips = (nx + STRIP - 1) / STRIP;
@@ -283,7 +262,7 @@ lbm_status lbm_moments(lbm_handle* h, double* d_rho, double* d_ux, double* d_uy,
   if (!h) return fail(LBM_EINVAL, "handle is NULL");
   Field F = field_of(h, h->cur);
   dim3 grid((h->p.nx + 63) / 64, h->p.ny);
-  hipLaunchKernelGGL(k_moments, grid, dim3(64), 0, h->stream, F, d_rho, d_ux, d_uy, d_T, d_p);
+  hipLaunchKernelGGL(k_moments<0>, grid, dim3(64), 0, h->stream, F, d_rho, d_ux, d_uy, d_T, d_p);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "k_moments launch");
   return LBM_OK;

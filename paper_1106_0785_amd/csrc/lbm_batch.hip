@@ -1,0 +1,446 @@
+// C ABI of the batched form (declarations and contracts in include/lbm_batch.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/lbm_batch.h"
+#include "lbm_batch_kernels.h"
+#include "lbm_internal.h"
+
+using namespace lbm;
+
+namespace {
+
+constexpr int MIN_CHUNK = 32;
+
+struct Schedule {
+  int region;  // 128 or 256 nodes per workgroup region
+  int h;       // time steps per launch
+};
+
+bool schedule_ok(const Schedule& s) {
+  return (s.region == 128 || s.region == 256) && s.h >= 1 && s.region - 2 * s.h >= MIN_CHUNK;
+}
+
+template <int VER, int REGION>
+void launch_line(const double* A, double* B, const LineInst* insts, const LineChunk* chunks, int nchunks,
+                 const int* budget, int n0, int h, int* flag, hipStream_t st) {
+  hipLaunchKernelGGL((k_batch_line<VER, REGION>), dim3(nchunks), dim3(REGION), 0, st, A, B, insts, chunks, budget, n0, h,
+                     flag);
+}
+
+}  // namespace
+
+struct lbm_batch {
+  int n;
+  std::vector<lbm_params> params;
+  std::vector<LineInst> host_insts;
+  std::vector<long long> node_off;  // offset of instance i in concatenated field arrays
+  long long total_nodes;
+  long long arena_doubles;
+  hipStream_t stream;
+  double* arena[2];
+  double* backup;
+  LineInst* insts;
+  LineChunk* chunks;
+  int max_chunks;
+  int* budget;
+  int* flag;
+  int cur;
+  Schedule sched;
+  int use_graph;
+  // chunk ranges per equilibrium version (1..3): [begin, end)
+  int vbegin[4], vend[4];
+  // cached graph
+  hipGraphExec_t graph[2];
+  int64_t graph_steps[2];
+};
+
+static long long line_len(const lbm_params& p) { return (long long)p.nx * p.ny; }
+
+static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+struct Layout {
+  size_t arena_bytes, insts_off, chunks_off, budget_off, flag_off, backup_off, total;
+  long long arena_doubles;
+  int max_chunks;
+};
+
+static lbm_status layout_of(const lbm_params* inst, int32_t n, Layout* L) {
+  if (!inst || n < 1) return fail(LBM_EINVAL, "need at least one instance");
+  long long dbl = 0, maxc = 0;
+  for (int i = 0; i < n; ++i) {
+    lbm_status st = validate(&inst[i]);
+    if (st != LBM_OK) return fail(st, "instance %d: %s", i, lbm_last_error());
+    const lbm_params& p = inst[i];
+    if (p.nx != 1 && p.ny != 1)
+      return fail(LBM_EINVAL, "instance %d is %d x %d: the batched form takes one-dimensional problems (nx == 1 or ny == 1)",
+                  i, p.nx, p.ny);
+    const long long N = line_len(p);
+    const int axis = (p.ny == 1 && p.nx > 1) ? 0 : 1;
+    if (p.bc[2 * axis] == LBM_BC_PERIODIC && N > 128)
+      return fail(LBM_EINVAL, "instance %d: a periodic line in the batch must have <= 128 nodes", i);
+    dbl += 16 * ((N + 15) / 16 * 16);
+    maxc += (N + MIN_CHUNK - 1) / MIN_CHUNK + 1;
+  }
+  L->arena_doubles = dbl;
+  L->max_chunks = (int)maxc;
+  L->arena_bytes = align256((size_t)dbl * sizeof(double));
+  L->insts_off = 2 * L->arena_bytes;
+  L->chunks_off = L->insts_off + align256((size_t)n * sizeof(LineInst));
+  L->budget_off = L->chunks_off + align256((size_t)maxc * sizeof(LineChunk));
+  L->flag_off = L->budget_off + align256((size_t)n * sizeof(int));
+  L->backup_off = L->flag_off + 256;
+  L->total = L->backup_off + L->arena_bytes;
+  return LBM_OK;
+}
+
+static void drop_graphs(lbm_batch* b) {
+  for (int k = 0; k < 2; ++k) {
+    if (b->graph[k]) hipGraphExecDestroy(b->graph[k]);
+    b->graph[k] = nullptr;
+    b->graph_steps[k] = -1;
+  }
+}
+
+// Builds the chunk list for the schedule (grouped by equilibrium version) and uploads it.
+static lbm_status build_chunks(lbm_batch* b, const Schedule& s) {
+  std::vector<LineChunk> ch;
+  for (int ver = 1; ver <= 3; ++ver) {
+    b->vbegin[ver] = (int)ch.size();
+    for (int i = 0; i < b->n; ++i) {
+      if (b->params[i].eq_version != ver) continue;
+      const int N = b->host_insts[i].N;
+      if (N <= s.region) {
+        ch.push_back(LineChunk{i, 0, N, 0});
+      } else {
+        const int C = s.region - 2 * s.h;
+        for (int st = 0; st < N; st += C) ch.push_back(LineChunk{i, st, std::min(C, N - st), 0});
+      }
+    }
+    b->vend[ver] = (int)ch.size();
+  }
+  if ((int)ch.size() > b->max_chunks) return fail(LBM_EINVAL, "schedule needs more chunks than reserved");
+  hipError_t e = hipMemcpyAsync(b->chunks, ch.data(), ch.size() * sizeof(LineChunk), hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return hip_fail(e, "uploading the chunk list");
+  b->sched = s;
+  drop_graphs(b);
+  return LBM_OK;
+}
+
+static hipError_t enqueue_steps(lbm_batch* b, int64_t nsteps, int start_cur) {
+  int cur = start_cur;
+  for (int64_t n0 = 0; n0 < nsteps; n0 += b->sched.h) {
+    const int h = (int)std::min<int64_t>(b->sched.h, nsteps - n0);
+    for (int ver = 1; ver <= 3; ++ver) {
+      const int nc = b->vend[ver] - b->vbegin[ver];
+      if (nc == 0) continue;
+      const LineChunk* c = b->chunks + b->vbegin[ver];
+      const double* A = b->arena[cur];
+      double* B = b->arena[cur ^ 1];
+      const bool big = b->sched.region == 256;
+#define LBM_LAUNCH(V)                                                                              \
+  if (big)                                                                                         \
+    launch_line<V, 256>(A, B, b->insts, c, nc, b->budget, (int)n0, h, b->flag, b->stream);         \
+  else                                                                                             \
+    launch_line<V, 128>(A, B, b->insts, c, nc, b->budget, (int)n0, h, b->flag, b->stream);
+      if (ver == 1) {
+        LBM_LAUNCH(1)
+      } else if (ver == 2) {
+        LBM_LAUNCH(2)
+      } else {
+        LBM_LAUNCH(3)
+      }
+#undef LBM_LAUNCH
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    cur ^= 1;
+  }
+  return hipSuccess;
+}
+
+static int launches_for(const lbm_batch* b, int64_t nsteps) {
+  return (int)((nsteps + b->sched.h - 1) / b->sched.h);
+}
+
+extern "C" {
+
+size_t lbm_batch_workspace_bytes(const lbm_params* inst, int32_t n) {
+  Layout L;
+  if (layout_of(inst, n, &L) != LBM_OK) return 0;
+  return L.total;
+}
+
+lbm_status lbm_batch_create(const lbm_params* inst, int32_t n, void* d_workspace, size_t ws_bytes, void* hip_stream,
+                            lbm_batch** out) {
+  if (!out) return fail(LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  Layout L;
+  lbm_status st = layout_of(inst, n, &L);
+  if (st != LBM_OK) return st;
+  if (!d_workspace || ((uintptr_t)d_workspace) % 256) return fail(LBM_EINVAL, "workspace must be 256-byte aligned");
+  if (ws_bytes < L.total) return fail(LBM_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
+  lbm_batch* b = new (std::nothrow) lbm_batch;
+  if (!b) return fail(LBM_ENOMEM, "host allocation failed");
+  b->n = n;
+  b->params.assign(inst, inst + n);
+  b->stream = (hipStream_t)hip_stream;
+  char* base = (char*)d_workspace;
+  b->arena[0] = (double*)base;
+  b->arena[1] = (double*)(base + L.arena_bytes);
+  b->insts = (LineInst*)(base + L.insts_off);
+  b->chunks = (LineChunk*)(base + L.chunks_off);
+  b->budget = (int*)(base + L.budget_off);
+  b->flag = (int*)(base + L.flag_off);
+  b->backup = (double*)(base + L.backup_off);
+  b->max_chunks = L.max_chunks;
+  b->arena_doubles = L.arena_doubles;
+  b->cur = 0;
+  b->use_graph = 1;
+  b->graph[0] = b->graph[1] = nullptr;
+  b->graph_steps[0] = b->graph_steps[1] = -1;
+  b->host_insts.resize(n);
+  b->node_off.resize(n);
+  long long off = 0, node = 0;
+  for (int i = 0; i < n; ++i) {
+    const lbm_params& p = inst[i];
+    LineInst& I = b->host_insts[i];
+    std::memset(&I, 0, sizeof(I));
+    I.N = (int)line_len(p);
+    I.stride = (I.N + 15) / 16 * 16;
+    I.off = off;
+    I.axis = (p.ny == 1 && p.nx > 1) ? 0 : 1;
+    I.walls = has_walls(&p) ? 1 : 0;
+    make_coef(&p, &I.hot, &I.cold);
+    off += 16LL * I.stride;
+    b->node_off[i] = node;
+    node += I.N;
+  }
+  b->total_nodes = node;
+  std::vector<int> budget(n, INT_MAX);
+  hipError_t e = hipMemcpyAsync(b->insts, b->host_insts.data(), n * sizeof(LineInst), hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(b->budget, budget.data(), n * sizeof(int), hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(b->flag, 0, 256, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) {
+    delete b;
+    return hip_fail(e, "uploading the batch description");
+  }
+  st = build_chunks(b, Schedule{256, 16});
+  if (st != LBM_OK) {
+    delete b;
+    return st;
+  }
+  *out = b;
+  clear_error();
+  return LBM_OK;
+}
+
+int64_t lbm_batch_offset(const lbm_batch* b, int32_t i) {
+  if (!b || i < 0 || i > b->n) return -1;
+  return i == b->n ? b->total_nodes : b->node_off[i];
+}
+
+lbm_status lbm_batch_init(lbm_batch* b, const double* d_rho, const double* d_ux, const double* d_uy,
+                          const double* d_T) {
+  if (!b || !d_rho || !d_ux || !d_uy || !d_T) return fail(LBM_EINVAL, "NULL argument");
+  for (int i = 0; i < b->n; ++i) {
+    const lbm_params& p = b->params[i];
+    const LineInst& I = b->host_insts[i];
+    const long long k = b->node_off[i];
+    for (int buf = 0; buf < 2; ++buf) {
+      Field F;
+      F.fin = nullptr;
+      F.fout = b->arena[buf] + I.off;
+      F.nx = p.nx;
+      F.ny = p.ny;
+      F.pitch = p.nx;
+      F.plane = I.stride;
+      dim3 grid((p.nx + 63) / 64, p.ny);
+      auto kern = p.eq_version == 2 ? k_init<2> : p.eq_version == 3 ? k_init<3> : k_init<1>;
+      hipLaunchKernelGGL(kern, grid, dim3(64), 0, b->stream, F, d_rho + k, d_ux + k, d_uy + k, d_T + k);
+    }
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "k_init launch");
+  b->cur = 0;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_set_budgets(lbm_batch* b, const int64_t* steps) {
+  if (!b) return fail(LBM_EINVAL, "batch is NULL");
+  std::vector<int> budget(b->n, INT_MAX);
+  if (steps)
+    for (int i = 0; i < b->n; ++i) {
+      if (steps[i] < 0) return fail(LBM_EINVAL, "budget of instance %d is negative", i);
+      budget[i] = (int)std::min<int64_t>(steps[i], INT_MAX);
+    }
+  hipError_t e = hipMemcpyAsync(b->budget, budget.data(), b->n * sizeof(int), hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return hip_fail(e, "uploading budgets");
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps) {
+  if (!b) return fail(LBM_EINVAL, "batch is NULL");
+  if (nsteps < 0 || nsteps > INT_MAX) return fail(LBM_EINVAL, "nsteps out of range");
+  if (nsteps == 0) return LBM_OK;
+  const int L = launches_for(b, nsteps);
+  if (!b->use_graph) {
+    hipError_t e = enqueue_steps(b, nsteps, b->cur);
+    if (e != hipSuccess) return hip_fail(e, "batched step launch");
+  } else {
+    const int c = b->cur;
+    if (b->graph_steps[c] != nsteps) {
+      if (b->graph[c]) hipGraphExecDestroy(b->graph[c]);
+      b->graph[c] = nullptr;
+      hipGraph_t g;
+      hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+      e = enqueue_steps(b, nsteps, c);
+      hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+      if (e != hipSuccess) return hip_fail(e, "capturing the batched steps");
+      if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+      e = hipGraphInstantiate(&b->graph[c], g, nullptr, nullptr, 0);
+      hipGraphDestroy(g);
+      if (e != hipSuccess) {
+        b->graph[c] = nullptr;
+        return hip_fail(e, "hipGraphInstantiate");
+      }
+      b->graph_steps[c] = nsteps;
+    }
+    hipError_t e = hipGraphLaunch(b->graph[c], b->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  }
+  if (L & 1) b->cur ^= 1;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_moments(lbm_batch* b, double* d_rho, double* d_ux, double* d_uy, double* d_T, double* d_p) {
+  if (!b) return fail(LBM_EINVAL, "batch is NULL");
+  for (int i = 0; i < b->n; ++i) {
+    const lbm_params& p = b->params[i];
+    const LineInst& I = b->host_insts[i];
+    const long long k = b->node_off[i];
+    Field F;
+    F.fin = b->arena[b->cur] + I.off;
+    F.fout = nullptr;
+    F.nx = p.nx;
+    F.ny = p.ny;
+    F.pitch = p.nx;
+    F.plane = I.stride;
+    dim3 grid((p.nx + 63) / 64, p.ny);
+    hipLaunchKernelGGL(k_moments<0>, grid, dim3(64), 0, b->stream, F, d_rho ? d_rho + k : nullptr,
+                       d_ux ? d_ux + k : nullptr, d_uy ? d_uy + k : nullptr, d_T ? d_T + k : nullptr,
+                       d_p ? d_p + k : nullptr);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "k_moments launch");
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_get_f(lbm_batch* b, double* d_f) {
+  if (!b || !d_f) return fail(LBM_EINVAL, "NULL argument");
+  for (int i = 0; i < b->n; ++i) {
+    const LineInst& I = b->host_insts[i];
+    hipError_t e = hipMemcpy2DAsync(d_f + 16 * b->node_off[i], I.N * sizeof(double), b->arena[b->cur] + I.off,
+                                    I.stride * sizeof(double), I.N * sizeof(double), 16, hipMemcpyDeviceToDevice,
+                                    b->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy2DAsync");
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_set_schedule(lbm_batch* b, int32_t region, int32_t steps_per_launch, int32_t use_graph) {
+  if (!b) return fail(LBM_EINVAL, "batch is NULL");
+  Schedule s{region, steps_per_launch};
+  if (!schedule_ok(s))
+    return fail(LBM_EINVAL, "schedule needs region in {128, 256} and region - 2 h >= %d", MIN_CHUNK);
+  b->use_graph = use_graph ? 1 : 0;
+  return build_chunks(b, s);
+}
+
+lbm_status lbm_batch_get_schedule(const lbm_batch* b, int32_t* region, int32_t* steps_per_launch,
+                                  int32_t* nchunks) {
+  if (!b) return fail(LBM_EINVAL, "batch is NULL");
+  if (region) *region = b->sched.region;
+  if (steps_per_launch) *steps_per_launch = b->sched.h;
+  if (nchunks) *nchunks = b->vend[3] - b->vbegin[1];
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_tune(lbm_batch* b, int64_t probe_steps, double* best_ms) {
+  if (!b) return fail(LBM_EINVAL, "batch is NULL");
+  if (probe_steps < 1) return fail(LBM_EINVAL, "probe_steps must be >= 1");
+  // keep the current state: every trial runs from a backup copy
+  const size_t bytes = (size_t)b->arena_doubles * sizeof(double);
+  hipError_t e = hipMemcpyAsync(b->backup, b->arena[b->cur], bytes, hipMemcpyDeviceToDevice, b->stream);
+  if (e != hipSuccess) return hip_fail(e, "backing up the state");
+  const int saved_cur = b->cur;
+  hipEvent_t t0, t1;
+  hipEventCreate(&t0);
+  hipEventCreate(&t1);
+  Schedule best{256, 16};
+  float best_t = 1e30f;
+  const int regions[2] = {128, 256};
+  const int hs[6] = {4, 8, 12, 16, 24, 32};
+  for (int r : regions)
+    for (int h : hs) {
+      Schedule s{r, h};
+      if (!schedule_ok(s)) continue;
+      if (build_chunks(b, s) != LBM_OK) continue;
+      // warm-up + timed trial, both without graphs
+      e = enqueue_steps(b, std::min<int64_t>(probe_steps, 2 * h), b->cur);
+      if (e == hipSuccess) e = hipEventRecord(t0, b->stream);
+      if (e == hipSuccess) e = enqueue_steps(b, probe_steps, b->cur);
+      if (e == hipSuccess) e = hipEventRecord(t1, b->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(t1);
+      if (e != hipSuccess) break;
+      float ms = 0;
+      hipEventElapsedTime(&ms, t0, t1);
+      if (ms < best_t) {
+        best_t = ms;
+        best = s;
+      }
+      // restore the state for the next trial
+      e = hipMemcpyAsync(b->arena[saved_cur], b->backup, bytes, hipMemcpyDeviceToDevice, b->stream);
+      if (e != hipSuccess) break;
+    }
+  hipEventDestroy(t0);
+  hipEventDestroy(t1);
+  if (e == hipSuccess) e = hipMemcpyAsync(b->arena[saved_cur], b->backup, bytes, hipMemcpyDeviceToDevice, b->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(b->flag, 0, sizeof(int), b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return hip_fail(e, "tuning run");
+  b->cur = saved_cur;
+  if (best_ms) *best_ms = best_t;
+  return build_chunks(b, best);
+}
+
+lbm_status lbm_batch_check(lbm_batch* b) {
+  if (!b) return fail(LBM_EINVAL, "batch is NULL");
+  int flag = 0;
+  hipError_t e = hipMemcpyAsync(&flag, b->flag, sizeof(int), hipMemcpyDeviceToHost, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return hip_fail(e, "reading the health flag");
+  if (flag) {
+    e = hipMemsetAsync(b->flag, 0, sizeof(int), b->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
+    return fail(LBM_ENONFINITE, "a batched step produced rho <= 0, T <= 0 or NaN");
+  }
+  return LBM_OK;
+}
+
+void lbm_batch_destroy(lbm_batch* b) {
+  if (!b) return;
+  drop_graphs(b);
+  delete b;
+}
+
+}  // extern "C"

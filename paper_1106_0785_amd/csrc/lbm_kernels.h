@@ -304,4 +304,27 @@ __global__ void k_init(Field F, const double* __restrict__ rho, const double* __
   for (int i = 0; i < 16; ++i) p[i * F.plane] = f[i];
 }
 
+// (template only so that every translation unit gets its own instance)
+template <int U>
+__global__ void k_moments(Field F, double* rho, double* ux, double* uy, double* T, double* P) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= F.nx) return;
+  const double* p = F.fin + (long long)y * F.pitch + x;
+  double f[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) f[i] = p[i * F.plane];
+  double m[16];
+  moments_from_f(f, m);
+  const double r = m[0], ir = 1.0 / r;
+  const double u = m[1] * ir, v = m[2] * ir;
+  const double t = m[3] * ir - 0.5 * (u * u + v * v);
+  const long long k = (long long)y * F.nx + x;
+  if (rho) rho[k] = r;
+  if (ux) ux[k] = u;
+  if (uy) uy[k] = v;
+  if (T) T[k] = t;
+  if (P) P[k] = r * t;
+}
+
 }  // namespace lbm

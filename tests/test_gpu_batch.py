@@ -1,0 +1,106 @@
+"""Batched form: every instance of an uneven batch ends where the
+single-problem path and the oracle put it; budgets, schedules and graph
+replays do not change results."""
+
+import numpy as np
+import pytest
+
+from gpu_util import assert_parity, field_errors, gpu_run, log, oracle_run
+from paper_1106_0785_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _batch(seed, n, **kw):
+    from paper_1106_0785_amd.batch import Batch
+
+    items = inputs.batch(seed=seed, n=n, **kw)
+    b = Batch([p for _, p, _ in items])
+    b.init([f for _, _, f in items])
+    return items, b
+
+
+def _moments_of(b, i):
+    m = {k: v.cpu().numpy() for k, v in b.moments().items()}
+    return {k: b.split(v, i) for k, v in m.items()}
+
+
+def test_batch_matches_single_problem_path_and_oracle():
+    items, b = _batch(3, 24, riemann_n=(200, 900), couette_h=(32, 120))
+    steps = 300
+    b.step(steps)
+    b.check()
+    fb = b.get_f().cpu().numpy()
+    worst = 0.0
+    for i, (kind, p, fl) in enumerate(items):
+        g, gf = gpu_run(p, fl, steps)
+        d = float(np.max(np.abs(b.f_of(fb, i) - gf) / np.abs(gf).max(axis=(1, 2), keepdims=True)))
+        worst = max(worst, d)
+        assert d <= 1e-13, (i, kind, d)
+        if i < 6:
+            o, _ = oracle_run(p, fl, steps)
+            assert_parity(_moments_of(b, i), o, what="batch instance %d (%s, %dx%d)" % (i, kind, p["nx"], p["ny"]))
+    log("batch vs single-problem kernels: max diff %.2e over %d instances" % (worst, len(items)))
+    b.close()
+
+
+@pytest.mark.parametrize("region,h", [(128, 8), (256, 16), (256, 32), (128, 1)])
+def test_schedules_agree(region, h):
+    items, b = _batch(5, 12, riemann_n=(300, 1500), couette_h=(40, 200))
+    b.set_schedule(region, h)
+    b.step(100)
+    f = b.get_f().cpu().numpy()
+    b.close()
+    items, r = _batch(5, 12, riemann_n=(300, 1500), couette_h=(40, 200))
+    r.set_schedule(256, 4, use_graph=False)
+    r.step(100)
+    ref = r.get_f().cpu().numpy()
+    r.close()
+    log("schedule (%d, %d) vs (256, 4): bitwise %s" % (region, h, np.array_equal(f, ref)))
+    assert np.array_equal(f, ref)
+
+
+def test_budgets():
+    items, b = _batch(7, 10, riemann_n=(256, 700), couette_h=(32, 90))
+    budgets = [17 * (i + 1) for i in range(len(items))]
+    b.set_budgets(budgets)
+    b.step(200)
+    fb = b.get_f().cpu().numpy()
+    for i, (kind, p, fl) in enumerate(items):
+        _, gf = gpu_run(p, fl, min(200, budgets[i]))
+        d = float(np.max(np.abs(b.f_of(fb, i) - gf) / np.abs(gf).max(axis=(1, 2), keepdims=True)))
+        assert d <= 1e-13, (i, budgets[i], d)
+    b.close()
+
+
+def test_graph_replays_match_eager_runs():
+    """The captured graph replayed several times, with eager work and
+    synchronisations in between, equals the same steps without a graph."""
+    import torch
+
+    items, g = _batch(9, 16, riemann_n=(256, 1200), couette_h=(32, 150))
+    items, e = _batch(9, 16, riemann_n=(256, 1200), couette_h=(32, 150))
+    g.set_schedule(256, 16, use_graph=True)
+    e.set_schedule(256, 16, use_graph=False)
+    for rep in range(4):
+        g.step(48)  # 3 launches: odd, so the graph alternates between buffers
+        e.step(48)
+        torch.cuda.synchronize()
+        _ = torch.ones(1000, device="cuda").sum().item()  # unrelated eager work
+        fg = g.get_f().cpu().numpy()
+        fe = e.get_f().cpu().numpy()
+        log("graph replay %d bitwise equal to eager: %s" % (rep, np.array_equal(fg, fe)))
+        assert np.array_equal(fg, fe)
+    g.close()
+    e.close()
+
+
+def test_tuner_keeps_state_and_picks_a_schedule():
+    items, b = _batch(11, 20)
+    f0 = b.get_f().cpu().numpy()
+    s = b.tune(probe_steps=32, use_cache=False)
+    log("tuner choice: %s" % s)
+    f1 = b.get_f().cpu().numpy()
+    assert np.array_equal(f0, f1)
+    assert s["region"] in (128, 256)
+    b.close()
