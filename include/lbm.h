@@ -125,10 +125,19 @@ lbm_status lbm_check(lbm_handle* h);
 
 /* Kernel variant used by lbm_step: 0 = the fused LDS-staged kernel (default),
  * 1 = the plain one-thread-per-node global-memory kernel (a reference for
- * race and indexing checks). Rows per workgroup tile for variant 0 via
- * lbm_set_tile (power of two, 1..16). */
+ * race and indexing checks). lbm_set_tile sets the rows per workgroup tile
+ * of variant 0 (1..1024, rounded up to a multiple of 4; results do not
+ * depend on it). */
 lbm_status lbm_set_variant(lbm_handle* h, int32_t variant);
 lbm_status lbm_set_tile(lbm_handle* h, int32_t rows);
+
+/* Tile-height tuner for variant 0: times probe_steps steps for each
+ * candidate tile height (synchronising the stream) and keeps the fastest
+ * (*rows_out, *best_ms may be NULL). With d_scratch (device, >= 16 ny pitch
+ * doubles) the state is saved and restored; with NULL the state advances. */
+lbm_status lbm_tune(lbm_handle* h, int64_t probe_steps, double* d_scratch, size_t scratch_bytes, int32_t* rows_out,
+                    double* best_ms);
+lbm_status lbm_get_tile(const lbm_handle* h, int32_t* rows);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* lbm_last_error(void);

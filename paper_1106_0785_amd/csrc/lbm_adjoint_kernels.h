@@ -1,0 +1,390 @@
+// Adjoint (reverse-mode) step of the MRT FD-LBM update, hand-written.
+//
+// One forward step is f^{n+1}(x) = f(x) + L(x) + M^-1 col(x), with the
+// per-axis Lax-Wendroff increments L, col_k = -dt s_k (m_k - q_k(c)) for the
+// non-conserved moments (c = rho, j_x, j_y, e) and the energy-flux
+// modification g_7, g_8 added to col_7, col_8 (Sec. II); g depends on the
+// node's c and on the central-difference velocity gradients A, B built from
+// the four neighbours' velocities. Its amplification matrix G_ij (Sec. III)
+// is this map's Jacobian in Fourier space. Given lambda = dL/df^{n+1}, the
+// adjoint step returns dL/df^n:
+//
+//   lambda^n_i(x) = lambda_i(x) + sum_axes [ p_i (lambda_i(x-e) - lambda_i(x))
+//                                          + m_i (lambda_i(x+e) - lambda_i(x)) ]
+//                 + (M^T nu)_i + (M_{1..4}^T g_c)_i
+//   mu  = M^-T lambda(x),   nu_k = -dt s_k mu_k  (k >= 5)
+//   g_c = - J_q^T nu + mu_7 dg_7/dc + mu_8 dg_8/dc + (du/dc)^T g_u
+//   g_u(x) = gathered from the neighbours' dL/dA, dL/dB (the modification's
+//            coupling to the velocities of the four neighbours)
+//
+// and accumulates dL/ds_k = sum_n sum_x mu_k d col_k/d s_k. Ghost layers
+// are transposed: a periodic ghost is the wrapped node, a mirror ghost
+// returns the mirrored lambda and (dL/dA, -dL/dB), a zero-gradient ghost
+// returns lambda with the Lax-Wendroff weights swapped and (-dL/dA, -dL/dB),
+// a fixed-state ghost returns nothing.
+#pragma once
+
+#include "lbm_dual.h"
+#include "lbm_kernels.h"
+
+namespace lbm {
+
+// Derivatives of the modification coefficients (Hot::cmod) w.r.t. the rates:
+// d cm0/d s5, d cm0/d s7, d cm1/d s6, d cm1/d s7, d cm2/d s6, d cm2/d s8,
+// d cm3/d s5, d cm3/d s8 (all 0 for the unmodified model).
+struct AdjCoef {
+  double dcm[8];
+  double mdt;  // -dt: d col_k / d s_k = -dt (m_k - q_k)
+};
+
+// Per-node record written by the first pass: dL/dA, dL/dB and the velocity.
+enum { REC_GA = 0, REC_GB = 1, REC_UX = 2, REC_UY = 3, NREC = 4 };
+
+LBM_HD void adj_record(const Field& F, const Hot& c, const double* __restrict__ lam, double* __restrict__ rec, int x,
+                       int y) {
+  const long long k = (long long)y * F.pitch + x;
+  double f[16], l[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    f[i] = F.fin[k + i * F.plane];
+    l[i] = lam[k + i * F.plane];
+  }
+  double m[16], mu[16];
+  moments_from_f(f, m);
+  minvt_apply(l, mu);
+  const double rho = m[0], ir = 1.0 / rho;
+  const double ux = m[1] * ir, uy = m[2] * ir;
+  const double T = m[3] * ir - 0.5 * (ux * ux + uy * uy);
+  const double rT = rho * T;
+  double vx, vy;
+  velocity_of(f, vx, vy);
+  rec[k + REC_GA * F.plane] = mu[6] * c.cmod[0] * rT * ux + mu[7] * c.cmod[3] * rT * uy;
+  rec[k + REC_GB * F.plane] = mu[6] * c.cmod[1] * rT * uy + mu[7] * c.cmod[2] * rT * ux;
+  rec[k + REC_UX * F.plane] = vx;
+  rec[k + REC_UY * F.plane] = vy;
+}
+
+template <int VER>
+__global__ __launch_bounds__(256) void k_adj_records(Field F, const double* __restrict__ lam,
+                                                     double* __restrict__ rec, const Hot* __restrict__ hot) {
+  __shared__ Hot hs;
+  stage_hot(hot, &hs);
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  if (x >= F.nx || y >= F.ny) return;
+  adj_record(F, hs, lam, rec, x, y);
+}
+
+// Record of stencil point (x + ox, y + oy) of node (x, y) as its ghost
+// transposition requires; ux, uy are the velocity the forward step used.
+LBM_HD void rec_point(const Field& F, const Hot& c, const Cold* __restrict__ cold,
+                                          const double* __restrict__ rec, int x, int y, int ox, int oy, double& GA,
+                                          double& GB, double& ux, double& uy) {
+  const int xn = x + ox, yn = y + oy;
+  const Src sx = resolve(xn, F.nx, c.bc[0], c.bc[1], 0);
+  const Src sy = resolve(yn, F.ny, c.bc[2], c.bc[3], 2);
+  // side whose ghost this stencil point is (-1: a stored node); periodic
+  // ghosts are stored nodes after wrapping
+  const int side = (xn < 0 || xn >= F.nx) ? sx.side : ((yn < 0 || yn >= F.ny) ? sy.side : -1);
+  const int kind = side >= 0 ? c.bc[side] : BC_PERIODIC;
+  if (kind == BC_DIRICHLET_EQ) {
+    GA = GB = 0.0;
+    velocity_of(cold->ghost[side], ux, uy);
+    return;
+  }
+  const long long k = (long long)sy.idx * F.pitch + sx.idx;
+  GA = rec[k + REC_GA * F.plane];
+  GB = rec[k + REC_GB * F.plane];
+  ux = rec[k + REC_UX * F.plane];
+  uy = rec[k + REC_UY * F.plane];
+  if (kind == BC_SPECULAR) {
+    GB = -GB;
+    if (side < 2)
+      ux = -ux;
+    else
+      uy = -uy;
+  } else if (kind == BC_ZERO_GRADIENT) {
+    GA = -GA;
+    GB = -GB;
+  }
+}
+
+// lambda at stencil point (x + ox, y + oy) for the transposed convection
+// (mirror ghosts permuted, fixed-state ghosts zero; a zero-gradient ghost
+// returns the node's own lambda and the caller swaps the weights).
+LBM_HD void lam_point(const Field& F, const Hot& c, const double* __restrict__ lam, int x, int y,
+                                          int ox, int oy, double* l) {
+  const Src sx = resolve(x + ox, F.nx, c.bc[0], c.bc[1], 0);
+  const Src sy = resolve(y + oy, F.ny, c.bc[2], c.bc[3], 2);
+  if (sx.mode == 2 || sy.mode == 2) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) l[i] = 0.0;
+    return;
+  }
+  const long long k = (long long)sy.idx * F.pitch + sx.idx;
+  double t[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) t[i] = lam[k + i * F.plane];
+  if (sx.mode == 1) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) l[i] = t[MIRROR_X[i]];
+  } else if (sy.mode == 1) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) l[i] = t[MIRROR_Y[i]];
+  } else {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) l[i] = t[i];
+  }
+}
+
+// Transposed Lax-Wendroff increment of velocity I along one axis; v is the
+// velocity component, (pm, mm) the weights as the forward step applies them
+// to (f(x+e) - f, f(x-e) - f), zl/zh true when the low/high neighbour is a
+// zero-gradient ghost.
+LBM_HD double conv_t_axis(int v, const double* lc, double lo, double hi, double lam, bool zl,
+                                              bool zh) {
+  // weights of f(x+e) (p) and f(x-e) (m) for this velocity
+  double p = 0.0, m = 0.0;
+  if (v == 1) { p = lc[0]; m = lc[1]; }
+  if (v == -1) { p = lc[1]; m = lc[0]; }
+  if (v == 2) { p = lc[2]; m = lc[3]; }
+  if (v == -2) { p = lc[3]; m = lc[2]; }
+  // node x is the + neighbour of x-e (weight p) and the - neighbour of x+e (weight m)
+  double r = p * (lo - lam) + m * (hi - lam);
+  if (zl) r += (m - p) * lam;  // ghost x-e = f(x): node x itself used weight m on it
+  if (zh) r += (p - m) * lam;  // ghost x+e = f(x): weight p
+  return r;
+}
+
+// New adjoint lambda^n at node (x, y) into lam_out; adds this node's
+// contribution to dL/ds_5..16 (index k - 5) into sg.
+template <int VER>
+LBM_HD void adj_node(const Field& F, const Hot& c, const Cold* __restrict__ cold, const AdjCoef* __restrict__ adj,
+                     const double* __restrict__ lam_in, double* __restrict__ lam_out, const double* __restrict__ rec,
+                     int x, int y, double* sg) {
+  const long long k0 = (long long)y * F.pitch + x;
+  double f[16], l[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    f[i] = F.fin[k0 + i * F.plane];
+    l[i] = lam_in[k0 + i * F.plane];
+  }
+  // --- forward quantities at the node
+  double m[16];
+  moments_from_f(f, m);
+  const double rho = m[0], ir = 1.0 / rho;
+  const double ux = m[1] * ir, uy = m[2] * ir;
+  const double T = m[3] * ir - 0.5 * (ux * ux + uy * uy);
+  const double rT = rho * T;
+  double q[16];
+  equilibrium_moments<VER, double>(m[0], m[1], m[2], m[3], q);
+  // --- neighbour records: velocities for A, B and dL/dA, dL/dB
+  double GAxp, GBxp, uxxp, uyxp, GAxm, GBxm, uxxm, uyxm, GAyp, GByp, uxyp, uyyp, GAym, GBym, uxym, uyym;
+  rec_point(F, c, cold, rec, x, y, +1, 0, GAxp, GBxp, uxxp, uyxp);
+  rec_point(F, c, cold, rec, x, y, -1, 0, GAxm, GBxm, uxxm, uyxm);
+  rec_point(F, c, cold, rec, x, y, 0, +1, GAyp, GByp, uxyp, uyyp);
+  rec_point(F, c, cold, rec, x, y, 0, -1, GAym, GBym, uxym, uyym);
+  const double A = (uxxp - uxxm) * c.inv2dx - (uyyp - uyym) * c.inv2dy;
+  const double B = (uyxp - uyxm) * c.inv2dx + (uxyp - uxym) * c.inv2dy;
+  // --- collision adjoint
+  double mu[16], nu[16];
+  minvt_apply(l, mu);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) nu[k] = 0.0;
+#pragma unroll
+  for (int k = 4; k < 16; ++k) nu[k] = c.cq[k - 4] * mu[k];
+  // conserved-moment adjoint: -J_q^T nu + mu7 dg7/dc + mu8 dg8/dc, by dual numbers
+  double gc[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    Dual cc[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) cc[b] = Dual(m[b], a == b ? 1.0 : 0.0);
+    Dual qd[16];
+    equilibrium_moments<VER, Dual>(cc[0], cc[1], cc[2], cc[3], qd);
+    double s = 0.0;
+#pragma unroll
+    for (int k = 4; k < 16; ++k) s -= nu[k] * qd[k].d;
+    const Dual iR = 1.0 / cc[0];
+    const Dual vxd = cc[1] * iR, vyd = cc[2] * iR;
+    const Dual Td = cc[3] * iR - 0.5 * (vxd * vxd + vyd * vyd);
+    const Dual rTd = cc[0] * Td;
+    const Dual g7 = c.cmod[0] * rTd * vxd * A + c.cmod[1] * rTd * vyd * B;
+    const Dual g8 = c.cmod[2] * rTd * vxd * B + c.cmod[3] * rTd * vyd * A;
+    gc[a] = s + mu[6] * g7.d + mu[7] * g8.d;
+  }
+  // velocity adjoint from the neighbours' gradient terms, then du/dc
+  const double gux = (GAxm - GAxp) * c.inv2dx + (GBym - GByp) * c.inv2dy;
+  const double guy = (GBxm - GBxp) * c.inv2dx - (GAym - GAyp) * c.inv2dy;
+  {
+    double r0, jx0, jy0;
+    density_momentum(f, r0, jx0, jy0);
+    const double ir0 = 1.0 / r0;
+    const double vx0 = jx0 * ir0, vy0 = jy0 * ir0;
+    gc[0] += -(vx0 * gux + vy0 * guy) * ir0;
+    gc[1] += gux * ir0;
+    gc[2] += guy * ir0;
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) nu[k] = gc[k];
+  double out[16];
+  mt_apply(nu, out);
+  // --- transposed convection and identity
+  double lxp[16], lxm[16], lyp[16], lym[16];
+  lam_point(F, c, lam_in, x, y, +1, 0, lxp);
+  lam_point(F, c, lam_in, x, y, -1, 0, lxm);
+  lam_point(F, c, lam_in, x, y, 0, +1, lyp);
+  lam_point(F, c, lam_in, x, y, 0, -1, lym);
+  const bool zxl = x == 0 && c.bc[0] == BC_ZERO_GRADIENT, zxh = x == F.nx - 1 && c.bc[1] == BC_ZERO_GRADIENT;
+  const bool zyl = y == 0 && c.bc[2] == BC_ZERO_GRADIENT, zyh = y == F.ny - 1 && c.bc[3] == BC_ZERO_GRADIENT;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    double v = out[i];
+    if (VX[i] != 0) v += conv_t_axis(VX[i], c.lx, lxm[i], lxp[i], l[i], zxl, zxh);
+    if (VY[i] != 0) v += conv_t_axis(VY[i], c.ly, lym[i], lyp[i], l[i], zyl, zyh);
+    out[i] = l[i] + v;
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) lam_out[k0 + i * F.plane] = out[i];
+  // --- dL/ds: d col_k/d s_k = -dt (m_k - q_k), plus the modification's
+  // coefficients (their s-derivatives already carry the factor dt)
+#pragma unroll
+  for (int k = 4; k < 16; ++k) sg[k - 4] = mu[k] * adj->mdt * (m[k] - q[k]);
+  const double a7 = rT * ux * A, b7 = rT * uy * B, b8 = rT * ux * B, a8 = rT * uy * A;
+  sg[0] += mu[6] * adj->dcm[0] * a7 + mu[7] * adj->dcm[6] * a8;   // s5
+  sg[1] += mu[6] * adj->dcm[2] * b7 + mu[7] * adj->dcm[4] * b8;   // s6
+  sg[2] += mu[6] * (adj->dcm[1] * a7 + adj->dcm[3] * b7);          // s7
+  sg[3] += mu[7] * (adj->dcm[5] * b8 + adj->dcm[7] * a8);          // s8
+}
+
+template <int VER>
+__global__ __launch_bounds__(256) void k_adj_step(Field F, const double* __restrict__ lam_in,
+                                                  double* __restrict__ lam_out, const double* __restrict__ rec,
+                                                  const Hot* __restrict__ hot, const Cold* __restrict__ cold,
+                                                  const AdjCoef* __restrict__ adj, double* __restrict__ partials) {
+  __shared__ Hot hs;
+  __shared__ double red[12][256];
+  stage_hot(hot, &hs);
+  const int t = threadIdx.y * blockDim.x + threadIdx.x;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  double sg[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) sg[k] = 0.0;
+  if (x < F.nx && y < F.ny) adj_node<VER>(F, hs, cold, adj, lam_in, lam_out, rec, x, y, sg);
+  // deterministic block reduction, one slot per block, accumulated over steps
+#pragma unroll
+  for (int k = 0; k < 12; ++k) red[k][t] = sg[k];
+  __syncthreads();
+  const int nthr = blockDim.x * blockDim.y;
+  if (t < 12) {
+    double s = 0.0;
+    for (int j = 0; j < nthr; ++j) s += red[t][j];
+    const long long slot = (long long)blockIdx.y * gridDim.x + blockIdx.x;
+    partials[slot * 12 + t] += s;
+  }
+}
+
+}  // namespace lbm
+
+namespace lbm {
+
+// lambda at the final level from dL/d(rho, u_x, u_y, T) of the final fields
+// (any gradient pointer may be NULL); the fields are rho = m1, u = (m2, m3)/m1,
+// T = m4/m1 - |u|^2/2 (R = 1).
+LBM_HD void adj_final_node(const Field& F, const double* __restrict__ g_rho, const double* __restrict__ g_ux,
+                           const double* __restrict__ g_uy, const double* __restrict__ g_T, double* __restrict__ lam,
+                           int x, int y) {
+  const long long k = (long long)y * F.pitch + x;
+  const long long d = (long long)y * F.nx + x;
+  double f[16], m[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) f[i] = F.fin[k + i * F.plane];
+  moments_from_f(f, m);
+  const double r = m[0], ir = 1.0 / r;
+  const double gr = g_rho ? g_rho[d] : 0.0, gu = g_ux ? g_ux[d] : 0.0, gv = g_uy ? g_uy[d] : 0.0,
+               gt = g_T ? g_T[d] : 0.0;
+  double nu[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) nu[i] = 0.0;
+  const double ux = m[1] * ir, uy = m[2] * ir;
+  nu[0] = gr - (gu * ux + gv * uy) * ir + gt * (-m[3] * ir * ir + (ux * ux + uy * uy) * ir);
+  nu[1] = gu * ir - gt * ux * ir;
+  nu[2] = gv * ir - gt * uy * ir;
+  nu[3] = gt * ir;
+  double l[16];
+  mt_apply(nu, l);
+#pragma unroll
+  for (int i = 0; i < 16; ++i) lam[k + i * F.plane] = l[i];
+}
+
+template <int U>
+__global__ void k_adj_final(Field F, const double* __restrict__ g_rho, const double* __restrict__ g_ux,
+                            const double* __restrict__ g_uy, const double* __restrict__ g_T, double* __restrict__ lam) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= F.nx) return;
+  adj_final_node(F, g_rho, g_ux, g_uy, g_T, lam, x, y);
+}
+
+// dL/d(rho0, u0, T0) from lambda^0: f^0 = M^-1 q(rho, rho u, rho (T + u^2/2)).
+template <int VER>
+LBM_HD void adj_init_node(const Field& F, const double* __restrict__ lam, const double* __restrict__ rho,
+                          const double* __restrict__ ux, const double* __restrict__ uy, const double* __restrict__ T,
+                          double* g_rho, double* g_ux, double* g_uy, double* g_T, int x, int y) {
+  const long long k = (long long)y * F.pitch + x;
+  const long long d = (long long)y * F.nx + x;
+  double l[16], mu[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) l[i] = lam[k + i * F.plane];
+  minvt_apply(l, mu);
+  const double p0[4] = {rho[d], ux[d], uy[d], T[d]};
+  double g[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    Dual pv[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) pv[b] = Dual(p0[b], a == b ? 1.0 : 0.0);
+    const Dual jx = pv[0] * pv[1], jy = pv[0] * pv[2];
+    const Dual e = pv[0] * (pv[3] + 0.5 * (pv[1] * pv[1] + pv[2] * pv[2]));
+    Dual q[16];
+    equilibrium_moments<VER, Dual>(pv[0], jx, jy, e, q);
+    double s = 0.0;
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) s += mu[kk] * q[kk].d;
+    g[a] = s;
+  }
+  if (g_rho) g_rho[d] = g[0];
+  if (g_ux) g_ux[d] = g[1];
+  if (g_uy) g_uy[d] = g[2];
+  if (g_T) g_T[d] = g[3];
+}
+
+template <int VER>
+__global__ void k_adj_init(Field F, const double* __restrict__ lam, const double* __restrict__ rho,
+                           const double* __restrict__ ux, const double* __restrict__ uy, const double* __restrict__ T,
+                           double* g_rho, double* g_ux, double* g_uy, double* g_T) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= F.nx) return;
+  adj_init_node<VER>(F, lam, rho, ux, uy, T, g_rho, g_ux, g_uy, g_T, x, y);
+}
+
+// dL/ds_1..16 from the per-block partials (fixed summation order).
+template <int U>
+__global__ void k_adj_reduce(const double* __restrict__ partials, int nslots, double* __restrict__ grad_s) {
+  const int k = threadIdx.x;
+  if (k >= 16) return;
+  double s = 0.0;
+  if (k >= 4)
+    for (int b = 0; b < nslots; ++b) s += partials[(long long)b * 12 + (k - 4)];
+  grad_s[k] = s;
+}
+
+template <int U>
+__global__ void k_zero(double* p, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+}  // namespace lbm

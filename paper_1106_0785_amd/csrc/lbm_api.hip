@@ -30,6 +30,7 @@ lbm_status fail(lbm_status s, const char* fmt, ...) {
 }
 
 lbm_status hip_fail(hipError_t e, const char* what) {
+  (void)hipGetLastError();  // reset HIP's sticky last error so later launch checks do not see it
   return fail(LBM_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
@@ -312,6 +313,64 @@ lbm_status lbm_set_tile(lbm_handle* h, int32_t rows) {
   if (!h) return fail(LBM_EINVAL, "handle is NULL");
   if (rows < 1 || rows > 1024) return fail(LBM_EINVAL, "rows must be in 1..1024");
   h->rows = rows;
+  return LBM_OK;
+}
+
+lbm_status lbm_tune(lbm_handle* h, int64_t probe_steps, double* d_scratch, size_t scratch_bytes, int32_t* rows_out,
+                    double* best_ms) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (probe_steps < 1) return fail(LBM_EINVAL, "probe_steps must be >= 1");
+  const size_t state = 16 * (size_t)h->plane * sizeof(double);
+  if (d_scratch && scratch_bytes < state) return fail(LBM_EINVAL, "scratch needs %zu bytes", state);
+  hipError_t e = hipSuccess;
+  if (d_scratch) e = hipMemcpyAsync(d_scratch, h->f[h->cur], state, hipMemcpyDeviceToDevice, h->stream);
+  if (e != hipSuccess) return hip_fail(e, "saving the state");
+  const int saved_cur = h->cur, saved_variant = h->variant;
+  h->variant = 0;
+  hipEvent_t t0, t1;
+  hipEventCreate(&t0);
+  hipEventCreate(&t1);
+  const int cand[] = {4, 8, 12, 16, 20, 24, 28, 32, 40, 48, 56, 64, 96, 128};
+  int best = h->rows, last_rows = -1;
+  float best_t = 1e30f;
+  for (int r : cand) {
+    const MarchGeom g = march_geom(h->p.nx, h->p.ny, r);
+    if (g.rows == last_rows) continue;  // same tiling as a smaller candidate
+    last_rows = g.rows;
+    h->rows = g.rows;
+    lbm_status st = lbm_step(h, 2);  // warm-up
+    if (st != LBM_OK) break;
+    e = hipEventRecord(t0, h->stream);
+    if (e == hipSuccess) st = lbm_step(h, probe_steps);
+    if (e == hipSuccess) e = hipEventRecord(t1, h->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(t1);
+    if (e != hipSuccess || st != LBM_OK) break;
+    float ms = 0;
+    hipEventElapsedTime(&ms, t0, t1);
+    if (ms < best_t) {
+      best_t = ms;
+      best = g.rows;
+    }
+  }
+  hipEventDestroy(t0);
+  hipEventDestroy(t1);
+  h->variant = saved_variant;
+  h->rows = best;
+  if (e != hipSuccess) return hip_fail(e, "tuning run");
+  if (d_scratch) {
+    h->cur = saved_cur;
+    e = hipMemcpyAsync(h->f[h->cur], d_scratch, state, hipMemcpyDeviceToDevice, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(e, "restoring the state");
+  }
+  if (rows_out) *rows_out = best;
+  if (best_ms) *best_ms = best_t;
+  return LBM_OK;
+}
+
+lbm_status lbm_get_tile(const lbm_handle* h, int32_t* rows) {
+  if (!h || !rows) return fail(LBM_EINVAL, "NULL argument");
+  *rows = h->rows;
   return LBM_OK;
 }
 

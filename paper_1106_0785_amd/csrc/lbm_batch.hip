@@ -43,6 +43,7 @@ struct lbm_batch {
   long long total_nodes;
   long long arena_doubles;
   hipStream_t stream;
+  hipStream_t capture;  // private stream the graph is captured on (the caller's may be the null stream)
   double* arena[2];
   double* backup;
   LineInst* insts;
@@ -133,7 +134,7 @@ static lbm_status build_chunks(lbm_batch* b, const Schedule& s) {
   return LBM_OK;
 }
 
-static hipError_t enqueue_steps(lbm_batch* b, int64_t nsteps, int start_cur) {
+static hipError_t enqueue_steps(lbm_batch* b, int64_t nsteps, int start_cur, hipStream_t stream) {
   int cur = start_cur;
   for (int64_t n0 = 0; n0 < nsteps; n0 += b->sched.h) {
     const int h = (int)std::min<int64_t>(b->sched.h, nsteps - n0);
@@ -146,9 +147,9 @@ static hipError_t enqueue_steps(lbm_batch* b, int64_t nsteps, int start_cur) {
       const bool big = b->sched.region == 256;
 #define LBM_LAUNCH(V)                                                                              \
   if (big)                                                                                         \
-    launch_line<V, 256>(A, B, b->insts, c, nc, b->budget, (int)n0, h, b->flag, b->stream);         \
+    launch_line<V, 256>(A, B, b->insts, c, nc, b->budget, (int)n0, h, b->flag, stream);            \
   else                                                                                             \
-    launch_line<V, 128>(A, B, b->insts, c, nc, b->budget, (int)n0, h, b->flag, b->stream);
+    launch_line<V, 128>(A, B, b->insts, c, nc, b->budget, (int)n0, h, b->flag, stream);
       if (ver == 1) {
         LBM_LAUNCH(1)
       } else if (ver == 2) {
@@ -205,6 +206,11 @@ lbm_status lbm_batch_create(const lbm_params* inst, int32_t n, void* d_workspace
   b->use_graph = 1;
   b->graph[0] = b->graph[1] = nullptr;
   b->graph_steps[0] = b->graph_steps[1] = -1;
+  b->capture = nullptr;
+  if (hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking) != hipSuccess) {
+    delete b;
+    return hip_fail(hipGetLastError(), "creating the capture stream");
+  }
   b->host_insts.resize(n);
   b->node_off.resize(n);
   long long off = 0, node = 0;
@@ -229,11 +235,13 @@ lbm_status lbm_batch_create(const lbm_params* inst, int32_t n, void* d_workspace
   if (e == hipSuccess) e = hipMemsetAsync(b->flag, 0, 256, b->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) {
+    hipStreamDestroy(b->capture);
     delete b;
     return hip_fail(e, "uploading the batch description");
   }
   st = build_chunks(b, Schedule{256, 16});
   if (st != LBM_OK) {
+    hipStreamDestroy(b->capture);
     delete b;
     return st;
   }
@@ -293,18 +301,19 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps) {
   if (nsteps == 0) return LBM_OK;
   const int L = launches_for(b, nsteps);
   if (!b->use_graph) {
-    hipError_t e = enqueue_steps(b, nsteps, b->cur);
+    hipError_t e = enqueue_steps(b, nsteps, b->cur, b->stream);
     if (e != hipSuccess) return hip_fail(e, "batched step launch");
   } else {
     const int c = b->cur;
     if (b->graph_steps[c] != nsteps) {
       if (b->graph[c]) hipGraphExecDestroy(b->graph[c]);
       b->graph[c] = nullptr;
-      hipGraph_t g;
-      hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal);
       if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-      e = enqueue_steps(b, nsteps, c);
-      hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+      e = enqueue_steps(b, nsteps, c, b->capture);
+      hipError_t e2 = hipStreamEndCapture(b->capture, &g);
+      if ((e != hipSuccess || e2 != hipSuccess) && g) hipGraphDestroy(g);
       if (e != hipSuccess) return hip_fail(e, "capturing the batched steps");
       if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
       e = hipGraphInstantiate(&b->graph[c], g, nullptr, nullptr, 0);
@@ -396,9 +405,9 @@ lbm_status lbm_batch_tune(lbm_batch* b, int64_t probe_steps, double* best_ms) {
       if (!schedule_ok(s)) continue;
       if (build_chunks(b, s) != LBM_OK) continue;
       // warm-up + timed trial, both without graphs
-      e = enqueue_steps(b, std::min<int64_t>(probe_steps, 2 * h), b->cur);
+      e = enqueue_steps(b, std::min<int64_t>(probe_steps, 2 * h), b->cur, b->stream);
       if (e == hipSuccess) e = hipEventRecord(t0, b->stream);
-      if (e == hipSuccess) e = enqueue_steps(b, probe_steps, b->cur);
+      if (e == hipSuccess) e = enqueue_steps(b, probe_steps, b->cur, b->stream);
       if (e == hipSuccess) e = hipEventRecord(t1, b->stream);
       if (e == hipSuccess) e = hipEventSynchronize(t1);
       if (e != hipSuccess) break;
@@ -440,6 +449,7 @@ lbm_status lbm_batch_check(lbm_batch* b) {
 void lbm_batch_destroy(lbm_batch* b) {
   if (!b) return;
   drop_graphs(b);
+  if (b->capture) hipStreamDestroy(b->capture);
   delete b;
 }
 

@@ -86,6 +86,14 @@ __device__ __forceinline__ void store_node(const Field& F, int x, int y, const d
   for (int i = 0; i < 16; ++i) p[i * F.plane] = v[i];
 }
 
+// Streaming store of a node's new distributions: they are not read again in
+// this launch, so keep them from displacing halo rows in the caches.
+__device__ __forceinline__ void store_node_stream(const Field& F, int x, int y, const double* v) {
+  double* p = F.fout + (long long)y * F.pitch + x;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) __builtin_nontemporal_store(v[i], p + i * F.plane);
+}
+
 // Writes the NEQ wall node(s) fed by interior node (x, y) whose new
 // distributions are `out`.
 template <int VER>
@@ -243,13 +251,22 @@ __global__ __launch_bounds__(64 * WAVES, 2) void k_step_fused(Field F, const Hot
     }
   }
 
+  // Each wave keeps two rows in flight: `cur` (written to the ring at the
+  // end of this iteration) and `nxt` (issued now, written next iteration),
+  // so a load has two compute phases to arrive. The loop is unrolled twice so
+  // the two register buffers swap roles without copies.
+  double fa[16], fb[16];
+  bool ha, hb = false;
+  {
+    const int yn = y0 + WAVES + 1 + w;
+    ha = yn <= y1;
+    if (ha) load_point(F, cold, sx, resolve(yn, F.ny, c.bc[2], c.bc[3], 2), fa);
+  }
   bool ok = true;
-  for (int Y = y0; Y < y1; Y += WAVES) {
-    // prefetch the row that replaces row Y-1+w in the ring
-    const int yn = Y + WAVES + 1 + w;
-    const bool have = yn <= y1;
-    double fn[16];
-    if (have) load_point(F, cold, sx, resolve(yn, F.ny, c.bc[2], c.bc[3], 2), fn);
+  auto iteration = [&](int Y, double* cur, bool hcur, double* nxt, bool& hnxt) {
+    const int yn2 = Y + 2 * WAVES + 1 + w;
+    hnxt = yn2 <= y1;
+    if (hnxt) load_point(F, cold, sx, resolve(yn2, F.ny, c.bc[2], c.bc[3], 2), nxt);
     __syncthreads();
     const int y = Y + w;
     if (y < y1 && out_lane && (!WALLS || !is_wall_node(c, x, y, F.nx, F.ny))) {
@@ -270,19 +287,25 @@ __global__ __launch_bounds__(64 * WAVES, 2) void k_step_fused(Field F, const Hot
       nv.ux_ym = ring[sm][16][lane];
       nv.uy_ym = ring[sm][17][lane];
       ok &= collide_add<VER>(c, f, nv, out);
-      store_node(F, x, y, out);
+      store_node_stream(F, x, y, out);
       if (WALLS) walls_from<VER>(F, c, cold, x, y, out);
     }
     __syncthreads();
-    if (have) {
+    if (hcur) {
+      const int yn = Y + WAVES + 1 + w;
       double ux, uy;
-      velocity_of(fn, ux, uy);
+      velocity_of(cur, ux, uy);
       const int sn = (yn - base) % RING;
 #pragma unroll
-      for (int i = 0; i < 16; ++i) ring[sn][i][lane] = fn[i];
+      for (int i = 0; i < 16; ++i) ring[sn][i][lane] = cur[i];
       ring[sn][16][lane] = ux;
       ring[sn][17][lane] = uy;
     }
+  };
+  for (int Y = y0; Y < y1; Y += 2 * WAVES) {
+    iteration(Y, fa, ha, fb, hb);
+    if (Y + WAVES >= y1) break;
+    iteration(Y + WAVES, fb, hb, fa, ha);
   }
   if (!ok) flag[0] = 1;
 }

@@ -88,7 +88,7 @@ LBM_HD bool collide_add(const Hot& c, const double* f, const NbrVel& nv, double*
   moments_from_f(f, m);
   const double rho = m[0], jx = m[1], jy = m[2], e = m[3];
   double q[16];
-  equilibrium_moments<VER>(rho, jx, jy, e, q);
+  equilibrium_moments<VER, double>(rho, jx, jy, e, q);
   double col[16];
 #pragma unroll
   for (int k = 4; k < 16; ++k) col[k] = c.cq[k - 4] * (m[k] - q[k]);

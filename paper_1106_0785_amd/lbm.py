@@ -79,6 +79,9 @@ def load():
             "lbm_check": ([P], ctypes.c_int),
             "lbm_set_variant": ([P, ctypes.c_int32], ctypes.c_int),
             "lbm_set_tile": ([P, ctypes.c_int32], ctypes.c_int),
+            "lbm_tune": ([P, ctypes.c_int64, P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int32),
+                          ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+            "lbm_get_tile": ([P, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
             "lbm_last_error": ([], ctypes.c_char_p),
             "lbm_destroy": ([P], None),
         }
@@ -164,6 +167,21 @@ def lbm_set_tile(h, rows):
     _check(load().lbm_set_tile(h, int(rows)))
 
 
+def lbm_tune(h, probe_steps, scratch=None):
+    rows = ctypes.c_int32()
+    ms = ctypes.c_double()
+    sp = ctypes.c_void_p(scratch.data_ptr()) if scratch is not None else None
+    nbytes = scratch.numel() * scratch.element_size() if scratch is not None else 0
+    _check(load().lbm_tune(h, int(probe_steps), sp, nbytes, ctypes.byref(rows), ctypes.byref(ms)))
+    return rows.value, ms.value
+
+
+def lbm_get_tile(h):
+    rows = ctypes.c_int32()
+    _check(load().lbm_get_tile(h, ctypes.byref(rows)))
+    return rows.value
+
+
 def lbm_destroy(h):
     load().lbm_destroy(h)
 
@@ -230,6 +248,19 @@ class Simulation:
 
     def set_tile(self, rows):
         lbm_set_tile(self.handle, rows)
+
+    def tile(self):
+        return lbm_get_tile(self.handle)
+
+    def tune(self, probe_steps=20, keep_state=True):
+        """Pick the fastest tile height; with keep_state the state is saved
+        to a scratch tensor and restored."""
+        import torch
+
+        scratch = None
+        if keep_state:
+            scratch = torch.empty(16 * self.ny * ((self.nx + 63) // 64 * 64), dtype=torch.float64, device=self.device)
+        return lbm_tune(self.handle, probe_steps, scratch)
 
     def close(self):
         if getattr(self, "handle", None) is not None:

@@ -1,0 +1,167 @@
+"""The hand-written adjoint against the oracle's complex-step derivatives
+(exact up to rounding) and against central finite differences of the GPU
+forward path, on small problems with every supported boundary kind and on
+the 512 x 128, 2000-step shock/interface configuration."""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import log
+from paper_1106_0785_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _adjoint_directional(p, fl, steps, w_rho, w_T, d_fields, d_logs, ckpt=0):
+    """dL along (d_fields, d_logs) for L = sum(w_rho * rho_T) + sum(w_T * T_T)."""
+    from paper_1106_0785_amd.autograd import Adjoint
+
+    torch = _torch()
+    a = Adjoint(p, steps, ckpt)
+    f0 = [torch.from_numpy(np.ascontiguousarray(fl[k])).cuda() for k in ("rho", "ux", "uy", "T")]
+    a.forward(*f0)
+    grads, gs = a.backward(torch.from_numpy(w_rho).cuda(), None, None, torch.from_numpy(w_T).cuda())
+    grads = [g.cpu().numpy() for g in grads]
+    gs = gs.cpu().numpy()
+    s = np.array(p["s"])
+    a.close()
+    dl = sum(float(np.sum(g * d)) for g, d in zip(grads, d_fields))
+    return dl + float(np.sum(gs * s * d_logs)), gs
+
+
+def _complex_step(p, fl, steps, w_rho, w_T, d_fields, d_logs):
+    h = 1e-30
+    keys = ("rho", "ux", "uy", "T")
+    cf = {k: fl[k] + 1j * h * d for k, d in zip(keys, d_fields)}
+    f = oracle.init_complex(p, cf["rho"], cf["ux"], cf["uy"], cf["T"])
+    s = np.array(p["s"])
+    f = oracle.run_complex(p, f, steps, s_im=h * s * d_logs)
+    m = oracle.moments_complex(p, f)
+    return float(np.sum(w_rho * m["rho"].imag) + np.sum(w_T * m["T"].imag)) / h
+
+
+CASES = {
+    "specular_x_periodic_y": (["specular", "specular", "periodic", "periodic"], {}),
+    "zero_gradient_x_specular_y": (["zero_gradient", "zero_gradient", "specular", "specular"], {}),
+    "dirichlet_x": (["dirichlet_eq", "zero_gradient", "periodic", "periodic"], {}),
+    "unmodified_periodic": (["periodic"] * 4, {"modified": 0}),
+    "version2_periodic": (["periodic"] * 4, {"eq_version": 2}),
+    "printed_sign": (["specular", "specular", "periodic", "periodic"], {"modified": 2}),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_adjoint_matches_complex_step(name):
+    bc, kw = CASES[name]
+    p, fl = inputs.smooth_periodic(seed=13, nx=23, ny=17, amp=0.06, **kw)
+    p["bc"] = bc
+    p["wall"][0] = [1.03, 0.02, 0.0, 1.01]
+    p["s"][4], p["s"][5], p["s"][6], p["s"][7] = 700.0, 900.0, 1200.0, 1500.0
+    steps = 40
+    rng = np.random.default_rng(1)
+    w_rho = rng.standard_normal((17, 23))
+    w_T = rng.standard_normal((17, 23))
+    worst = 0.0
+    for trial in range(3):
+        d_fields = [rng.standard_normal((17, 23)) for _ in range(4)]
+        d_logs = rng.standard_normal(16)
+        got, gs = _adjoint_directional(p, fl, steps, w_rho, w_T, d_fields, d_logs, ckpt=7)
+        ref = _complex_step(p, fl, steps, w_rho, w_T, d_fields, d_logs)
+        rel = abs(got - ref) / abs(ref)
+        worst = max(worst, rel)
+        assert np.all(gs[:4] == 0.0)
+    log("adjoint vs complex step (%s): max rel diff %.2e" % (name, worst))
+    assert worst <= 1e-9
+
+
+def _rm_loss_setup(nx=512, ny=128, steps=2000):
+    torch = _torch()
+    p, fl, meta = inputs.rm(seed=0, nx=nx, ny=ny)
+    p_t, fl_t, meta_t = inputs.rm(seed=101, nx=nx, ny=ny, mach=meta["mach"])
+    from paper_1106_0785_amd import lbm
+
+    sim = lbm.Simulation(p_t)
+    sim.init(**fl_t)
+    sim.step(steps)
+    target = sim.moments()["rho"].clone()
+    sim.close()
+    return p, meta, target
+
+
+def _fields_of(a, meta, nx, ny):
+    torch = _torch()
+    return inputs.rm_fields(nx, ny, a, meta["mach"], meta["heavy"], meta["x0_cells"], meta["shock_cells"],
+                            meta["width_cells"], meta["wall_ramp_cells"], xp=torch)
+
+
+def _loss_forward(p, meta, target, a, log_s, steps):
+    """Loss of the plain forward path (no adjoint) for finite differences."""
+    from paper_1106_0785_amd import lbm
+
+    torch = _torch()
+    nx, ny = p["nx"], p["ny"]
+    f = _fields_of(a, meta, nx, ny)
+    q = dict(p, s=[math.exp(v) for v in log_s.tolist()])
+    sim = lbm.Simulation(q)
+    sim.init(f["rho"], f["ux"], f["uy"], f["T"])
+    sim.step(steps)
+    rho = sim.moments()["rho"]
+    sim.close()
+    return 0.5 * float(torch.sum((rho - target) ** 2))
+
+
+def test_rm_adjoint_finite_differences_and_timing():
+    """512 x 128 shock/interface, 2000 steps, sqrt(T) checkpoints; gradient
+    w.r.t. all log s_i and the per-row interface displacement a(y), checked by
+    central differences (h = 1e-6) along 8 seeded directions."""
+    import time
+
+    from paper_1106_0785_amd.autograd import simulate
+
+    torch = _torch()
+    nx, ny, steps = 512, 128, 2000
+    p, meta, target = _rm_loss_setup(nx, ny, steps)
+    a = torch.tensor(meta["a"], dtype=torch.float64, device="cuda", requires_grad=True)
+    log_s = torch.tensor(np.log(p["s"]), dtype=torch.float64, device="cuda", requires_grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    f = _fields_of(a, meta, nx, ny)
+    rho, ux, uy, T = simulate(f["rho"], f["ux"], f["uy"], f["T"], log_s, p, steps)
+    loss = 0.5 * torch.sum((rho - target) ** 2)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    loss.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    log("rm 512x128x2000: forward (checkpointed) %.3f s, backward %.3f s, ratio %.2f"
+        % (t1 - t0, t2 - t1, (t2 - t1) / (t1 - t0)))
+    ga = a.grad.detach().cpu().numpy()
+    gs = log_s.grad.detach().cpu().numpy()
+    a0 = a.detach().clone()
+    s0 = log_s.detach().clone()
+    rng = np.random.default_rng(8)
+    h = 1e-6
+    worst = 0.0
+    for k in range(8):
+        d = rng.standard_normal(ny + 16)
+        d /= np.linalg.norm(d)
+        da, ds = d[:ny], d[ny:]
+        adj = float(np.sum(ga * da) + np.sum(gs * ds))
+        dat = torch.tensor(da, dtype=torch.float64, device="cuda")
+        dst = torch.tensor(ds, dtype=torch.float64, device="cuda")
+        lp = _loss_forward(p, meta, target, a0 + h * dat, s0 + h * dst, steps)
+        lm = _loss_forward(p, meta, target, a0 - h * dat, s0 - h * dst, steps)
+        fd = (lp - lm) / (2 * h)
+        rel = abs(adj - fd) / max(abs(fd), 1e-300)
+        worst = max(worst, rel)
+        log("direction %d: adjoint %.10e  central FD %.10e  rel %.2e" % (k, adj, fd, rel))
+    assert worst <= 1e-6

@@ -26,6 +26,9 @@ def _moments_of(b, i):
 
 
 def test_batch_matches_single_problem_path_and_oracle():
+    """Every instance: moments within 1e-11 of the oracle; distributions within
+    rounding of the single-problem kernel (the two kernels contract
+    multiply-adds differently, and shock-tube runs amplify ulp differences)."""
     items, b = _batch(3, 24, riemann_n=(200, 900), couette_h=(32, 120))
     steps = 300
     b.step(steps)
@@ -36,10 +39,9 @@ def test_batch_matches_single_problem_path_and_oracle():
         g, gf = gpu_run(p, fl, steps)
         d = float(np.max(np.abs(b.f_of(fb, i) - gf) / np.abs(gf).max(axis=(1, 2), keepdims=True)))
         worst = max(worst, d)
-        assert d <= 1e-13, (i, kind, d)
-        if i < 6:
-            o, _ = oracle_run(p, fl, steps)
-            assert_parity(_moments_of(b, i), o, what="batch instance %d (%s, %dx%d)" % (i, kind, p["nx"], p["ny"]))
+        assert d <= 1e-12, (i, kind, d)
+        o, _ = oracle_run(p, fl, steps)
+        assert_parity(_moments_of(b, i), o, what="batch instance %d (%s, %dx%d)" % (i, kind, p["nx"], p["ny"]))
     log("batch vs single-problem kernels: max diff %.2e over %d instances" % (worst, len(items)))
     b.close()
 
@@ -66,10 +68,14 @@ def test_budgets():
     b.set_budgets(budgets)
     b.step(200)
     fb = b.get_f().cpu().numpy()
+    m = {k: v.cpu().numpy() for k, v in b.moments().items()}
     for i, (kind, p, fl) in enumerate(items):
-        _, gf = gpu_run(p, fl, min(200, budgets[i]))
+        n = min(200, budgets[i])
+        _, gf = gpu_run(p, fl, n)
         d = float(np.max(np.abs(b.f_of(fb, i) - gf) / np.abs(gf).max(axis=(1, 2), keepdims=True)))
-        assert d <= 1e-13, (i, budgets[i], d)
+        assert d <= 1e-12, (i, budgets[i], d)
+        o, _ = oracle_run(p, fl, n)
+        assert_parity({k: b.split(v, i) for k, v in m.items()}, o, what="budget %d instance %d" % (n, i))
     b.close()
 
 
