@@ -19,11 +19,14 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12  # bytes/s, MI355X HBM3E
 BYTES_PER_NODE = 256  # 16 FP64 reads + 16 FP64 writes per node update
+ADJ_BYTES_PER_NODE = 384  # adjoint step: lambda^{n+1} and f^n read, lambda^n written (16 FP64 each)
 KERNEL_SOURCES = ["paper_1106_0785_amd/csrc/lbm_kernels.h", "paper_1106_0785_amd/csrc/lbm_step.h",
                   "paper_1106_0785_amd/csrc/lbm_node.h", "paper_1106_0785_amd/csrc/lbm_consts.h"]
 
@@ -73,6 +76,99 @@ def run_problem(p, fields, steps, warmup, rows=None, tune=False):
     if tuned:
         out["tile_rows"] = tuned[0]
     return out
+
+
+def bench_batch(steps, seed=0, n=512):
+    """The 512-instance uneven batch: K steps of the batched form (autotuned
+    schedule, graph replays) against the same K steps of the plain path
+    called once per instance (lbm_step on each instance in turn)."""
+    import torch
+
+    from paper_1106_0785_amd import inputs, lbm
+    from paper_1106_0785_amd.batch import Batch
+
+    items = inputs.batch(seed=seed, n=n)
+    b = Batch([p for _, p, _ in items])
+    b.init([f for _, _, f in items])
+    sched = b.tune(probe_steps=32, use_cache=False)
+    nodes = b.total_nodes
+    b.step(steps)  # warm-up: graph capture for this step count
+    torch.cuda.synchronize()
+    b.init([f for _, _, f in items])
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    b.step(steps)
+    stop.record()
+    torch.cuda.synchronize()
+    tb = start.elapsed_time(stop) / 1e3
+    b.check()
+    b.close()
+
+    sims = []
+    for _, p, f in items:
+        s = lbm.Simulation(p)
+        s.init(**f)
+        sims.append(s)
+    for s in sims:
+        s.step(2)
+    torch.cuda.synchronize()
+    start.record()
+    for s in sims:
+        s.step(steps)
+    stop.record()
+    torch.cuda.synchronize()
+    tp = start.elapsed_time(stop) / 1e3
+    for s in sims:
+        s.check()
+        s.close()
+    mb = nodes * steps / tb / 1e6
+    mp = nodes * steps / tp / 1e6
+    return {"instances": n, "nodes": nodes, "steps": steps, "batched_seconds": tb, "plain_seconds": tp,
+            "batched_mlups": mb, "plain_mlups": mp, "batched_over_plain": mb / mp,
+            "batched_gbps_equivalent": mb * 1e6 * BYTES_PER_NODE / 1e9,
+            "schedule": {k: sched[k] for k in ("region", "steps_per_launch", "chunks")}}
+
+
+def bench_adjoint(nx=512, ny=128, steps=2000):
+    """Shock/interface problem at 512 x 128, 2000 steps: plain forward time
+    against the adjoint form's checkpointed forward and its backward sweep
+    (loss = half the squared misfit of the final density)."""
+    import torch
+
+    from paper_1106_0785_amd import inputs, lbm
+    from paper_1106_0785_amd.autograd import Adjoint
+
+    p, fl, meta = inputs.rm(seed=0, nx=nx, ny=ny)
+    sim = lbm.Simulation(p)
+    sim.init(**fl)
+    tf = time_steps(sim, steps, 20)
+    sim.check()
+    sim.close()
+
+    dev = torch.device("cuda")
+    f0 = [torch.from_numpy(np.ascontiguousarray(fl[k])).to(dev) for k in ("rho", "ux", "uy", "T")]
+    adj = Adjoint(p, steps)
+    adj.forward(*f0)  # warm-up
+    adj.backward(torch.ones(ny, nx, dtype=torch.float64, device=dev))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = adj.forward(*f0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    g = out["rho"] - 1.0
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    adj.backward(g)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    adj.close()
+    node_steps = nx * ny * steps
+    bwd_bytes = (ADJ_BYTES_PER_NODE + BYTES_PER_NODE) * node_steps
+    return {"nodes": nx * ny, "steps": steps, "plain_forward_seconds": tf,
+            "adjoint_forward_seconds": t1 - t0, "adjoint_backward_seconds": t3 - t2,
+            "backward_over_forward": (t3 - t2) / tf, "forward_plus_backward_over_forward": (t1 - t0 + t3 - t2) / tf,
+            "backward_gbps": bwd_bytes / (t3 - t2) / 1e9, "backward_hbm_frac": bwd_bytes / (t3 - t2) / HBM_PEAK,
+            "backward_algorithmic_bytes_per_node_step": ADJ_BYTES_PER_NODE + BYTES_PER_NODE}
 
 
 def traffic_from_profiles(kernel_name, workload):
@@ -148,6 +244,10 @@ def main():
         pr, flr, _ = inputs.riemann("sod", nx=2000, ny=4)
         log("riemann 2000x4")
         extra["riemann_2000x4"] = run_problem(pr, flr, 2000, 100)
+        log("batch: 512 uneven instances, batched form vs plain path")
+        extra["batch_512"] = bench_batch(1000)
+        log("adjoint rm 512x128, 2000 steps")
+        extra["adjoint_rm_512x128"] = bench_adjoint()
 
     kernel = "k_step_fused"
     workload = "rm_%dx%d" % (nx, ny)

@@ -187,12 +187,11 @@ def rm_fields(nx, ny, a_cells, mach, heavy, x0_cells, shock_cells, width_cells, 
     wall (a sharp velocity jump against the mirror ghost would excite
     grid-scale oscillations of the central stencil)."""
     rho2, du, p2, _ = post_shock(mach)
-    i = xp.arange(nx) + 0.5
     if xp is np:
-        ii = i[None, :]
-        aa = xp.asarray(a_cells)[:, None]
+        ii = (np.arange(nx) + 0.5)[None, :]
+        aa = np.asarray(a_cells)[:, None]
     else:
-        ii = i.to(a_cells.dtype)[None, :]
+        ii = (xp.arange(nx, dtype=a_cells.dtype, device=a_cells.device) + 0.5)[None, :]
         aa = a_cells[:, None]
     w_int = 0.5 * (1.0 + xp.tanh((ii - x0_cells - aa) / width_cells))    # 0 light -> 1 heavy
     w_sh = 0.5 * (1.0 + xp.tanh((ii - shock_cells) / width_cells)) + 0 * aa  # 0 shocked -> 1 quiet

@@ -54,3 +54,17 @@ def test_generators_are_seeded_and_shaped():
             assert p["ny"] == 1 and 256 <= p["nx"] <= 4096
         else:
             assert p["nx"] == 1 and 32 <= p["ny"] <= 256
+
+
+def test_rm_fields_torch_matches_numpy():
+    """The differentiable (torch) form of the shock/interface generator gives
+    the same fields as the numpy form, on the device of its argument."""
+    import torch
+
+    p, f, m = inputs.rm(seed=4, nx=64, ny=16)
+    a = torch.tensor(m["a"], dtype=torch.float64)
+    g = inputs.rm_fields(64, 16, a, m["mach"], m["heavy"], m["x0_cells"], m["shock_cells"], m["width_cells"],
+                         m["wall_ramp_cells"], xp=torch)
+    for k in f:
+        assert g[k].device == a.device
+        np.testing.assert_allclose(g[k].numpy(), f[k], rtol=0, atol=1e-14)
