@@ -46,12 +46,16 @@ LBM_HD Src resolve(int i, int n, int bc_lo, int bc_hi, int side_lo) {
   return s;
 }
 
-// Distributions of the stencil point (column sx, row sy) after ghost resolution.
-__device__ __forceinline__ void load_point(const Field& F, const Cold* __restrict__ cold, const Src& sx, const Src& sy,
-                                           double* f) {
-  const double* p = F.fin + (long long)sy.idx * F.pitch + sx.idx;
+// Raw distributions of stored node (col, row), no ghost treatment.
+__device__ __forceinline__ void load_raw(const Field& F, int col, int row, double* f) {
+  const double* p = F.fin + (long long)row * F.pitch + col;
 #pragma unroll
   for (int i = 0; i < 16; ++i) f[i] = p[i * F.plane];
+}
+
+// Turns the raw values of the stored node a ghost point reads into the ghost
+// values: mirrored velocities, or the fixed-state equilibrium.
+__device__ __forceinline__ void fix_ghost(const Cold* __restrict__ cold, const Src& sx, const Src& sy, double* f) {
   if (__builtin_expect((sx.mode | sy.mode) != 0, 0)) {
     if (sx.mode == 2 || sy.mode == 2) {
       const int side = (sx.mode == 2) ? sx.side : sy.side;
@@ -73,6 +77,13 @@ __device__ __forceinline__ void load_point(const Field& F, const Cold* __restric
       }
     }
   }
+}
+
+// Distributions of the stencil point (column sx, row sy) after ghost resolution.
+__device__ __forceinline__ void load_point(const Field& F, const Cold* __restrict__ cold, const Src& sx, const Src& sy,
+                                           double* f) {
+  load_raw(F, sx.idx, sy.idx, f);
+  fix_ghost(cold, sx, sy, f);
 }
 
 LBM_HD bool is_wall_node(const Hot& c, int x, int y, int nx, int ny) {
@@ -224,7 +235,9 @@ __global__ __launch_bounds__(64 * WAVES, 2) void k_step_fused(Field F, const Hot
   stage_hot(hot, &hs);
   const Hot& c = hs;
   const int lane = threadIdx.x & 63;
-  const int w = threadIdx.x >> 6;
+  // wave index and everything derived from rows are wave-uniform: keep them
+  // in scalar registers so row bookkeeping costs no vector registers
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int strip = tile % g.nstrips, seg = tile / g.nstrips;
   const int x = strip * STRIP - 1 + lane;
   const int y0 = seg * g.rows;
@@ -235,38 +248,48 @@ __global__ __launch_bounds__(64 * WAVES, 2) void k_step_fused(Field F, const Hot
   const int lm = lane > 0 ? lane - 1 : 0;
   const int lp = lane < 63 ? lane + 1 : 63;
   const int base = y0 - 1;  // row held in ring slot 0 at the start
+  // ghost rows below and above the domain (scalar reads of the BC codes)
+  const int bylo = __builtin_amdgcn_readfirstlane(hot->bc[2]);
+  const int byhi = __builtin_amdgcn_readfirstlane(hot->bc[3]);
+  const Src ylo = resolve(-1, F.ny, bylo, byhi, 2);
+  const Src yhi = resolve(F.ny, F.ny, bylo, byhi, 2);
+  auto ysrc = [&](int yr) -> Src { return yr < 0 ? ylo : (yr >= F.ny ? yhi : Src{yr, 0, -1}); };
+
+  auto to_ring = [&](int slot, double* f) {
+    double ux, uy;
+    velocity_of(f, ux, uy);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) ring[slot][i][lane] = f[i];
+    ring[slot][16][lane] = ux;
+    ring[slot][17][lane] = uy;
+  };
 
   // prologue: rows y0-1 .. y0+WAVES (only those <= y1 are ever read)
   for (int r = w; r < RING; r += WAVES) {
     const int yr = base + r;
     if (yr <= y1) {
       double f[16];
-      load_point(F, cold, sx, resolve(yr, F.ny, c.bc[2], c.bc[3], 2), f);
-      double ux, uy;
-      velocity_of(f, ux, uy);
-#pragma unroll
-      for (int i = 0; i < 16; ++i) ring[r][i][lane] = f[i];
-      ring[r][16][lane] = ux;
-      ring[r][17][lane] = uy;
+      load_point(F, cold, sx, ysrc(yr), f);
+      to_ring(r, f);
     }
   }
 
   // Each wave keeps two rows in flight: `cur` (written to the ring at the
   // end of this iteration) and `nxt` (issued now, written next iteration),
-  // so a load has two compute phases to arrive. The loop is unrolled twice so
-  // the two register buffers swap roles without copies.
+  // so a load has two compute phases to arrive. Loads are plain (no ghost
+  // treatment and no branch: a row past the tile end is clamped to the last
+  // row read and never stored); the ghost fix-up runs when the row enters
+  // the ring, after its data has arrived. The loop is unrolled twice so the
+  // two register buffers swap roles without copies.
   double fa[16], fb[16];
-  bool ha, hb = false;
   {
-    const int yn = y0 + WAVES + 1 + w;
-    ha = yn <= y1;
-    if (ha) load_point(F, cold, sx, resolve(yn, F.ny, c.bc[2], c.bc[3], 2), fa);
+    const int yn = min(y0 + WAVES + 1 + w, y1);
+    load_raw(F, sx.idx, ysrc(yn).idx, fa);
   }
   bool ok = true;
-  auto iteration = [&](int Y, double* cur, bool hcur, double* nxt, bool& hnxt) {
-    const int yn2 = Y + 2 * WAVES + 1 + w;
-    hnxt = yn2 <= y1;
-    if (hnxt) load_point(F, cold, sx, resolve(yn2, F.ny, c.bc[2], c.bc[3], 2), nxt);
+  auto iteration = [&](int Y, double* cur, double* nxt) {
+    const int yn2 = min(Y + 2 * WAVES + 1 + w, y1);
+    load_raw(F, sx.idx, ysrc(yn2).idx, nxt);
     __syncthreads();
     const int y = Y + w;
     if (y < y1 && out_lane && (!WALLS || !is_wall_node(c, x, y, F.nx, F.ny))) {
@@ -291,21 +314,16 @@ __global__ __launch_bounds__(64 * WAVES, 2) void k_step_fused(Field F, const Hot
       if (WALLS) walls_from<VER>(F, c, cold, x, y, out);
     }
     __syncthreads();
-    if (hcur) {
-      const int yn = Y + WAVES + 1 + w;
-      double ux, uy;
-      velocity_of(cur, ux, uy);
-      const int sn = (yn - base) % RING;
-#pragma unroll
-      for (int i = 0; i < 16; ++i) ring[sn][i][lane] = cur[i];
-      ring[sn][16][lane] = ux;
-      ring[sn][17][lane] = uy;
+    const int yn = Y + WAVES + 1 + w;
+    if (yn <= y1) {
+      fix_ghost(cold, sx, ysrc(yn), cur);
+      to_ring((yn - base) % RING, cur);
     }
   };
   for (int Y = y0; Y < y1; Y += 2 * WAVES) {
-    iteration(Y, fa, ha, fb, hb);
+    iteration(Y, fa, fb);
     if (Y + WAVES >= y1) break;
-    iteration(Y + WAVES, fb, hb, fa, ha);
+    iteration(Y + WAVES, fb, fa);
   }
   if (!ok) flag[0] = 1;
 }
