@@ -187,6 +187,37 @@ def traffic_from_profiles(kernel_name, workload):
     return None
 
 
+def copy_ceiling(nx, ny, reps=20):
+    """Bandwidth of two plain copies of the distribution layout, as context
+    for the roofline: the library's streaming probe (the step kernel's access
+    pattern, no arithmetic) and a device-to-device copy (torch copy_)."""
+    import torch
+
+    from paper_1106_0785_amd import lbm
+
+    pitch = (nx + 63) // 64 * 64
+    n = 16 * ny * pitch
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    out = {"bytes_per_copy": 2 * n * 8}
+    for name, fn in (("stream_probe", lambda: lbm.lbm_stream_copy(a, b, nx, ny)), ("device_copy", lambda: b.copy_(a))):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) / 1e3)
+        t = sorted(ts)[len(ts) // 2]
+        out[name + "_gbps"] = 2 * n * 8 / t / 1e9
+    del a, b
+    return out
+
+
 def cpu_baseline(budget_s=15.0):
     """The oracle as it stands, on the host cores, on a bounded sample of the
     1024 x 256 shock/interface problem."""
@@ -249,6 +280,8 @@ def main():
         log("adjoint rm 512x128, 2000 steps")
         extra["adjoint_rm_512x128"] = bench_adjoint()
 
+    log("copy ceiling")
+    extra["copy_ceiling_%dx%d" % (nx, ny)] = copy_ceiling(nx, ny)
     kernel = "k_step_fused"
     workload = "rm_%dx%d" % (nx, ny)
     bytes_per_launch = BYTES_PER_NODE * nx * ny

@@ -139,6 +139,14 @@ lbm_status lbm_tune(lbm_handle* h, int64_t probe_steps, double* d_scratch, size_
                     double* best_ms);
 lbm_status lbm_get_tile(const lbm_handle* h, int32_t* rows);
 
+/* Diagnostic, not part of the method: copies the 16 pitched planes of an
+ * nx-by-ny field laid out like the distributions ([16][ny][pitch], pitch = nx
+ * rounded up to 64 doubles, padding included) from d_src to d_dst on
+ * hip_stream, with the step kernel's HBM access pattern and no arithmetic.
+ * Its bandwidth is the ceiling for a kernel with that access pattern.
+ * Both buffers hold 16 ny pitch doubles and must not overlap. */
+lbm_status lbm_stream_copy(const double* d_src, double* d_dst, int32_t nx, int32_t ny, void* hip_stream);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* lbm_last_error(void);
 

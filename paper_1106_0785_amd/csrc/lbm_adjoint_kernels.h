@@ -257,13 +257,29 @@ LBM_HD void adj_node(const Field& F, const Hot& c, const Cold* __restrict__ cold
   sg[3] += mu[7] * (adj->dcm[5] * b8 + adj->dcm[7] * a8);          // s8
 }
 
+// Value of lane l (uniform) of a wave.
+__device__ __forceinline__ double read_lane(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Sum over the 64 lanes of a wave in a fixed order (rows of 16 by DPP, then
+// the four row sums), so the result does not depend on timing.
+__device__ __forceinline__ double wave_sum(double v) {
+  v = row16_sum(v);
+  return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+}
+
+// Launched with 64 x 4 threads per block.
 template <int VER>
 __global__ __launch_bounds__(256) void k_adj_step(Field F, const double* __restrict__ lam_in,
                                                   double* __restrict__ lam_out, const double* __restrict__ rec,
                                                   const Hot* __restrict__ hot, const Cold* __restrict__ cold,
                                                   const AdjCoef* __restrict__ adj, double* __restrict__ partials) {
   __shared__ Hot hs;
-  __shared__ double red[12][256];
+  __shared__ double red[12][4];
   stage_hot(hot, &hs);
   const int t = threadIdx.y * blockDim.x + threadIdx.x;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -274,14 +290,14 @@ __global__ __launch_bounds__(256) void k_adj_step(Field F, const double* __restr
   if (x < F.nx && y < F.ny) adj_node<VER>(F, hs, cold, adj, lam_in, lam_out, rec, x, y, sg);
   // deterministic block reduction, one slot per block, accumulated over steps
 #pragma unroll
-  for (int k = 0; k < 12; ++k) red[k][t] = sg[k];
+  for (int k = 0; k < 12; ++k) {
+    const double w = wave_sum(sg[k]);
+    if ((t & 63) == 0) red[k][t >> 6] = w;
+  }
   __syncthreads();
-  const int nthr = blockDim.x * blockDim.y;
   if (t < 12) {
-    double s = 0.0;
-    for (int j = 0; j < nthr; ++j) s += red[t][j];
     const long long slot = (long long)blockIdx.y * gridDim.x + blockIdx.x;
-    partials[slot * 12 + t] += s;
+    partials[slot * 12 + t] += (red[t][0] + red[t][1]) + (red[t][2] + red[t][3]);
   }
 }
 

@@ -1,4 +1,5 @@
 // C ABI of the single-problem path (declarations and contracts in include/lbm.h).
+#include <climits>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -327,9 +328,14 @@ lbm_status lbm_tune(lbm_handle* h, int64_t probe_steps, double* d_scratch, size_
   if (e != hipSuccess) return hip_fail(e, "saving the state");
   const int saved_cur = h->cur, saved_variant = h->variant;
   h->variant = 0;
-  hipEvent_t t0, t1;
-  hipEventCreate(&t0);
-  hipEventCreate(&t1);
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  e = hipEventCreate(&t0);
+  if (e == hipSuccess) e = hipEventCreate(&t1);
+  if (e != hipSuccess) {
+    if (t0) (void)hipEventDestroy(t0);
+    h->variant = saved_variant;
+    return hip_fail(e, "hipEventCreate");
+  }
   const int cand[] = {4, 8, 12, 16, 20, 24, 28, 32, 40, 48, 56, 64, 96, 128};
   int best = h->rows, last_rows = -1;
   float best_t = 1e30f;
@@ -346,14 +352,15 @@ lbm_status lbm_tune(lbm_handle* h, int64_t probe_steps, double* d_scratch, size_
     if (e == hipSuccess) e = hipEventSynchronize(t1);
     if (e != hipSuccess || st != LBM_OK) break;
     float ms = 0;
-    hipEventElapsedTime(&ms, t0, t1);
+    e = hipEventElapsedTime(&ms, t0, t1);
+    if (e != hipSuccess) break;
     if (ms < best_t) {
       best_t = ms;
       best = g.rows;
     }
   }
-  hipEventDestroy(t0);
-  hipEventDestroy(t1);
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
   h->variant = saved_variant;
   h->rows = best;
   if (e != hipSuccess) return hip_fail(e, "tuning run");
@@ -377,5 +384,21 @@ lbm_status lbm_get_tile(const lbm_handle* h, int32_t* rows) {
 const char* lbm_last_error(void) { return g_err.c_str(); }
 
 void lbm_destroy(lbm_handle* h) { delete h; }
+
+
+lbm_status lbm_stream_copy(const double* d_src, double* d_dst, int32_t nx, int32_t ny, void* hip_stream) {
+  if (!d_src || !d_dst) return fail(LBM_EINVAL, "NULL argument");
+  if (nx < 1 || ny < 1) return fail(LBM_EINVAL, "nx and ny must be >= 1");
+  const long long pitch = row_pitch(nx);
+  const int rows = 32;
+  const int nstrips = (int)(pitch / STRIP);
+  const long long ntiles = (long long)nstrips * ((ny + rows - 1) / rows);
+  if (ntiles > INT_MAX) return fail(LBM_EINVAL, "field too large");
+  hipLaunchKernelGGL(k_stream_copy<0>, dim3((unsigned)ntiles), dim3(64 * WAVES), 0, (hipStream_t)hip_stream, d_src, d_dst,
+                     ny, pitch, rows, nstrips, (int)ntiles);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "k_stream_copy launch");
+  return LBM_OK;
+}
 
 }  // extern "C"

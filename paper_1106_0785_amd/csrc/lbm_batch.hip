@@ -102,7 +102,7 @@ static lbm_status layout_of(const lbm_params* inst, int32_t n, Layout* L) {
 
 static void drop_graphs(lbm_batch* b) {
   for (int k = 0; k < 2; ++k) {
-    if (b->graph[k]) hipGraphExecDestroy(b->graph[k]);
+    if (b->graph[k]) (void)hipGraphExecDestroy(b->graph[k]);
     b->graph[k] = nullptr;
     b->graph_steps[k] = -1;
   }
@@ -235,13 +235,13 @@ lbm_status lbm_batch_create(const lbm_params* inst, int32_t n, void* d_workspace
   if (e == hipSuccess) e = hipMemsetAsync(b->flag, 0, 256, b->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) {
-    hipStreamDestroy(b->capture);
+    (void)hipStreamDestroy(b->capture);
     delete b;
     return hip_fail(e, "uploading the batch description");
   }
   st = build_chunks(b, Schedule{256, 16});
   if (st != LBM_OK) {
-    hipStreamDestroy(b->capture);
+    (void)hipStreamDestroy(b->capture);
     delete b;
     return st;
   }
@@ -306,18 +306,18 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps) {
   } else {
     const int c = b->cur;
     if (b->graph_steps[c] != nsteps) {
-      if (b->graph[c]) hipGraphExecDestroy(b->graph[c]);
+      if (b->graph[c]) (void)hipGraphExecDestroy(b->graph[c]);
       b->graph[c] = nullptr;
       hipGraph_t g = nullptr;
       hipError_t e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal);
       if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
       e = enqueue_steps(b, nsteps, c, b->capture);
       hipError_t e2 = hipStreamEndCapture(b->capture, &g);
-      if ((e != hipSuccess || e2 != hipSuccess) && g) hipGraphDestroy(g);
+      if ((e != hipSuccess || e2 != hipSuccess) && g) (void)hipGraphDestroy(g);
       if (e != hipSuccess) return hip_fail(e, "capturing the batched steps");
       if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
       e = hipGraphInstantiate(&b->graph[c], g, nullptr, nullptr, 0);
-      hipGraphDestroy(g);
+      (void)hipGraphDestroy(g);
       if (e != hipSuccess) {
         b->graph[c] = nullptr;
         return hip_fail(e, "hipGraphInstantiate");
@@ -392,9 +392,13 @@ lbm_status lbm_batch_tune(lbm_batch* b, int64_t probe_steps, double* best_ms) {
   hipError_t e = hipMemcpyAsync(b->backup, b->arena[b->cur], bytes, hipMemcpyDeviceToDevice, b->stream);
   if (e != hipSuccess) return hip_fail(e, "backing up the state");
   const int saved_cur = b->cur;
-  hipEvent_t t0, t1;
-  hipEventCreate(&t0);
-  hipEventCreate(&t1);
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  e = hipEventCreate(&t0);
+  if (e == hipSuccess) e = hipEventCreate(&t1);
+  if (e != hipSuccess) {
+    if (t0) (void)hipEventDestroy(t0);
+    return hip_fail(e, "hipEventCreate");
+  }
   Schedule best{256, 16};
   float best_t = 1e30f;
   const int regions[2] = {128, 256};
@@ -412,7 +416,8 @@ lbm_status lbm_batch_tune(lbm_batch* b, int64_t probe_steps, double* best_ms) {
       if (e == hipSuccess) e = hipEventSynchronize(t1);
       if (e != hipSuccess) break;
       float ms = 0;
-      hipEventElapsedTime(&ms, t0, t1);
+      e = hipEventElapsedTime(&ms, t0, t1);
+      if (e != hipSuccess) break;
       if (ms < best_t) {
         best_t = ms;
         best = s;
@@ -421,8 +426,8 @@ lbm_status lbm_batch_tune(lbm_batch* b, int64_t probe_steps, double* best_ms) {
       e = hipMemcpyAsync(b->arena[saved_cur], b->backup, bytes, hipMemcpyDeviceToDevice, b->stream);
       if (e != hipSuccess) break;
     }
-  hipEventDestroy(t0);
-  hipEventDestroy(t1);
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
   if (e == hipSuccess) e = hipMemcpyAsync(b->arena[saved_cur], b->backup, bytes, hipMemcpyDeviceToDevice, b->stream);
   if (e == hipSuccess) e = hipMemsetAsync(b->flag, 0, sizeof(int), b->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
@@ -449,7 +454,7 @@ lbm_status lbm_batch_check(lbm_batch* b) {
 void lbm_batch_destroy(lbm_batch* b) {
   if (!b) return;
   drop_graphs(b);
-  if (b->capture) hipStreamDestroy(b->capture);
+  if (b->capture) (void)hipStreamDestroy(b->capture);
   delete b;
 }
 

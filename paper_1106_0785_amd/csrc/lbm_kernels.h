@@ -2,6 +2,8 @@
 // one-thread-per-node reference kernel, plus init / moments kernels.
 #pragma once
 
+#include <type_traits>
+
 #include "lbm_step.h"
 
 namespace lbm {
@@ -182,35 +184,68 @@ __global__ __launch_bounds__(256) void k_step_plain(Field F, const Hot* __restri
 }
 
 // ---------------------------------------------------------------------------
-// Fused kernel. A workgroup of WAVES wavefronts owns a tile of STRIP columns
-// by `rows` rows and marches up it WAVES rows at a time. The 64 lanes of a
-// wave hold columns x0-1 .. x0+62; lanes 0 and 63 are halo lanes (ghosts at
-// the domain edge) that produce no output. Rows y-1 .. y+WAVES live in a
-// ring of RING rows in LDS (16 distributions + velocity per lane), so each
-// distribution is read from HBM about once; each wave prefetches its next
-// row into registers while it computes the current one.
+// Fused kernel. A workgroup of WAVES wavefronts owns a tile of STRIP = 64
+// columns (one per lane, 512-byte aligned rows) by `rows` rows and marches up
+// it WAVES rows at a time. Rows y-1 .. y+WAVES live in a ring of RING rows in
+// LDS, each RW = 66 entries wide: the left neighbour column x0-1, the 64
+// strip columns, the right neighbour column x0+64, with 16 distributions and
+// the velocity per entry. Each distribution is read from HBM about once and
+// every lane stores a node (columns past nx land in the row padding), so the
+// stores are full, aligned lines. Each wave keeps its next row in flight in
+// registers while it computes the current one; the two neighbour columns of
+// a row come with one extra load (lane l holds plane l & 15 of the left
+// (l & 16 == 0) or right neighbour) and their velocities from a sum over the
+// 16 lanes of a DPP row.
 // ---------------------------------------------------------------------------
-constexpr int STRIP = 62;
+constexpr int STRIP = 64;
 constexpr int WAVES = 4;
 constexpr int RING = WAVES + 2;
 constexpr int NV = 18;  // 16 distributions + u_x + u_y per ring entry
+constexpr int RW = STRIP + 2;
 
 // Convection of all 16 velocities with the stencil values read from the LDS
-// ring rows (current row r0, rows above/below rp/rm) as they are needed.
+// ring rows (current row r0, rows above/below rp/rm) as they are needed; c0,
+// cp, cm are the ring columns of the node and its x+1 / x-1 neighbours.
 template <int I>
 struct ConvLds {
-  __device__ __forceinline__ static void run(const Hot& c, const double (*r0)[64], const double (*rp)[64],
-                                             const double (*rm)[64], int lane, int lp, int lm, double* out) {
-    out[I] = convect<I>(c, r0[I][lane], VX[I] ? r0[I][lp] : 0.0, VX[I] ? r0[I][lm] : 0.0,
-                        VY[I] ? rp[I][lane] : 0.0, VY[I] ? rm[I][lane] : 0.0);
-    ConvLds<I + 1>::run(c, r0, rp, rm, lane, lp, lm, out);
+  __device__ __forceinline__ static void run(const Hot& c, const double (*r0)[RW], const double (*rp)[RW],
+                                             const double (*rm)[RW], int c0, int cp, int cm, double* out) {
+    out[I] = convect<I>(c, r0[I][c0], VX[I] ? r0[I][cp] : 0.0, VX[I] ? r0[I][cm] : 0.0,
+                        VY[I] ? rp[I][c0] : 0.0, VY[I] ? rm[I][c0] : 0.0);
+    ConvLds<I + 1>::run(c, r0, rp, rm, c0, cp, cm, out);
   }
 };
 template <>
 struct ConvLds<16> {
-  __device__ __forceinline__ static void run(const Hot&, const double (*)[64], const double (*)[64],
-                                             const double (*)[64], int, int, int, double*) {}
+  __device__ __forceinline__ static void run(const Hot&, const double (*)[RW], const double (*)[RW],
+                                             const double (*)[RW], int, int, int, double*) {}
 };
+
+// Lane value from another lane of the same row of 16 (DPP control CTRL).
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Sum over each row of 16 lanes; every lane of the row gets the same value
+// (xor-1 and xor-2 quad swaps, then half-row and row mirrors).
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp_move<0xB1>(v);
+  v += dpp_move<0x4E>(v);
+  v += dpp_move<0x141>(v);
+  v += dpp_move<0x140>(v);
+  return v;
+}
+
+__device__ __forceinline__ int lane_table(const int (&t)[16], int i) {
+  int r = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) r = (i == k) ? t[k] : r;
+  return r;
+}
 
 struct MarchGeom {
   int nstrips;  // ceil(nx / STRIP)
@@ -228,7 +263,7 @@ __device__ __forceinline__ int xcd_tile(int b, const MarchGeom& g) { return (b %
 template <int VER, bool WALLS>
 __global__ __launch_bounds__(64 * WAVES, 2) void k_step_fused(Field F, const Hot* __restrict__ hot,
                                                                const Cold* __restrict__ cold, MarchGeom g, int* flag) {
-  __shared__ double ring[RING][NV][64];
+  __shared__ double ring[RING][NV][RW];
   __shared__ Hot hs;
   const int tile = xcd_tile(blockIdx.x, g);
   if (tile >= g.ntiles) return;  // whole workgroup leaves together
@@ -236,17 +271,17 @@ __global__ __launch_bounds__(64 * WAVES, 2) void k_step_fused(Field F, const Hot
   const Hot& c = hs;
   const int lane = threadIdx.x & 63;
   // wave index and everything derived from rows are wave-uniform: keep them
-  // in scalar registers so row bookkeeping costs no vector registers
+  // in scalar registers
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int strip = tile % g.nstrips, seg = tile / g.nstrips;
-  const int x = strip * STRIP - 1 + lane;
+  const int x0 = strip * STRIP;
+  const int x = x0 + lane;
   const int y0 = seg * g.rows;
   const int y1 = min(y0 + g.rows, F.ny);
-  // lanes right of the x = nx ghost lane idle on a valid column
+  // this lane's column: x = nx is the right ghost; lanes past it read column
+  // nx-1 and store into the row padding
   const Src sx = (x <= F.nx) ? resolve(x, F.nx, c.bc[0], c.bc[1], 0) : Src{F.nx - 1, 0, -1};
-  const bool out_lane = lane >= 1 && lane <= STRIP && x < F.nx;
-  const int lm = lane > 0 ? lane - 1 : 0;
-  const int lp = lane < 63 ? lane + 1 : 63;
+  const int c0 = lane + 1;  // ring column of this lane's node
   const int base = y0 - 1;  // row held in ring slot 0 at the start
   // ghost rows below and above the domain (scalar reads of the BC codes)
   const int bylo = __builtin_amdgcn_readfirstlane(hot->bc[2]);
@@ -255,77 +290,162 @@ __global__ __launch_bounds__(64 * WAVES, 2) void k_step_fused(Field F, const Hot
   const Src yhi = resolve(F.ny, F.ny, bylo, byhi, 2);
   auto ysrc = [&](int yr) -> Src { return yr < 0 ? ylo : (yr >= F.ny ? yhi : Src{yr, 0, -1}); };
 
-  auto to_ring = [&](int slot, double* f) {
+  // neighbour-column value of this lane: plane ep of column x0-1 (es = 0) or
+  // x0+64 (es = 1), with the x ghost rule folded into the address (mirror:
+  // mirrored plane; fixed state: the ghost value, same for every row). Only
+  // rows inside the domain use these columns, so no y ghost rule is needed.
+  const int ep = lane & 15, es = (lane >> 4) & 1;
+  const int ecol = es ? RW - 1 : 0;
+  const double* eptr;
+  long long estride;
+  {
+    const int ex = es ? x0 + STRIP : x0 - 1;
+    const Src e = (ex <= F.nx) ? resolve(ex, F.nx, c.bc[0], c.bc[1], 0) : Src{F.nx - 1, 0, -1};
+    if (e.mode == 2) {
+      eptr = &cold->ghost[e.side][ep];
+      estride = 0;
+    } else {
+      const int pl = (e.mode == 1) ? lane_table(MIRROR_X, ep) : ep;
+      eptr = F.fin + (long long)pl * F.plane + e.idx;
+      estride = F.pitch;
+    }
+  }
+  const double evx = (double)lane_table(VX, ep), evy = (double)lane_table(VY, ep);
+
+  auto to_ring = [&](int slot, const double* f, double e) {
     double ux, uy;
     velocity_of(f, ux, uy);
 #pragma unroll
-    for (int i = 0; i < 16; ++i) ring[slot][i][lane] = f[i];
-    ring[slot][16][lane] = ux;
-    ring[slot][17][lane] = uy;
+    for (int i = 0; i < 16; ++i) ring[slot][i][c0] = f[i];
+    ring[slot][16][c0] = ux;
+    ring[slot][17][c0] = uy;
+    // neighbour columns: every lane of a DPP row writes the same values
+    ring[slot][ep][ecol] = e;
+    const double er = row16_sum(e), ejx = row16_sum(evx * e), ejy = row16_sum(evy * e);
+    const double ir = 1.0 / er;
+    ring[slot][16][ecol] = ejx * ir;
+    ring[slot][17][ecol] = ejy * ir;
   };
 
   // prologue: rows y0-1 .. y0+WAVES (only those <= y1 are ever read)
   for (int r = w; r < RING; r += WAVES) {
     const int yr = base + r;
     if (yr <= y1) {
+      const Src sy = ysrc(yr);
       double f[16];
-      load_point(F, cold, sx, ysrc(yr), f);
-      to_ring(r, f);
+      load_point(F, cold, sx, sy, f);
+      const double e = eptr[sy.idx * estride];
+      to_ring(r, f, e);
     }
   }
 
   // Each wave keeps two rows in flight: `cur` (written to the ring at the
-  // end of this iteration) and `nxt` (issued now, written next iteration),
-  // so a load has two compute phases to arrive. Loads are plain (no ghost
-  // treatment and no branch: a row past the tile end is clamped to the last
-  // row read and never stored); the ghost fix-up runs when the row enters
-  // the ring, after its data has arrived. The loop is unrolled twice so the
-  // two register buffers swap roles without copies.
-  double fa[16], fb[16];
+  // end of this iteration) and `nxt` (issued now, written next iteration).
+  // Loads are plain (no ghost treatment, no branch: a row past the tile end
+  // is clamped to the last row read); the ghost fix-up runs when the row
+  // enters the ring, after its data has arrived. FULL iterations (every wave
+  // has a row to compute and one to enter) have no branches around stores
+  // and loads, so the waits before the ring entry cover only `cur`.
+  double fa[16], fb[16], ea, eb;
   {
     const int yn = min(y0 + WAVES + 1 + w, y1);
-    load_raw(F, sx.idx, ysrc(yn).idx, fa);
+    const int yi = ysrc(yn).idx;
+    load_raw(F, sx.idx, yi, fa);
+    ea = eptr[yi * estride];
   }
   bool ok = true;
-  auto iteration = [&](int Y, double* cur, double* nxt) {
-    const int yn2 = min(Y + 2 * WAVES + 1 + w, y1);
-    load_raw(F, sx.idx, ysrc(yn2).idx, nxt);
+  auto iteration = [&](auto full, int Y, double* cur, double& ecur, double* nxt, double& enxt) {
+    constexpr bool FULL = decltype(full)::value;
+    {
+      const int yi = ysrc(min(Y + 2 * WAVES + 1 + w, y1)).idx;
+      load_raw(F, sx.idx, yi, nxt);
+      enxt = eptr[yi * estride];
+    }
     __syncthreads();
     const int y = Y + w;
-    if (y < y1 && out_lane && (!WALLS || !is_wall_node(c, x, y, F.nx, F.ny))) {
-      const int s0 = (y - base) % RING, sp = (y + 1 - base) % RING, sm = (y - 1 - base) % RING;
-      double out[16];
-      // convection first, reading each neighbour value from LDS as it is used
-      ConvLds<0>::run(c, ring[s0], ring[sp], ring[sm], lane, lp, lm, out);
-      double f[16];
+    if (FULL || y < y1) {
+      if (!WALLS || !is_wall_node(c, x, y, F.nx, F.ny)) {
+        const int s0 = (y - base) % RING, sp = (y + 1 - base) % RING, sm = (y - 1 - base) % RING;
+        double out[16];
+        // convection first, reading each neighbour value from LDS as it is used
+        ConvLds<0>::run(c, ring[s0], ring[sp], ring[sm], c0, c0 + 1, c0 - 1, out);
+        double f[16];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) f[i] = ring[s0][i][lane];
-      NbrVel nv;
-      nv.ux_xp = ring[s0][16][lp];
-      nv.uy_xp = ring[s0][17][lp];
-      nv.ux_xm = ring[s0][16][lm];
-      nv.uy_xm = ring[s0][17][lm];
-      nv.ux_yp = ring[sp][16][lane];
-      nv.uy_yp = ring[sp][17][lane];
-      nv.ux_ym = ring[sm][16][lane];
-      nv.uy_ym = ring[sm][17][lane];
-      ok &= collide_add<VER>(c, f, nv, out);
-      store_node_stream(F, x, y, out);
-      if (WALLS) walls_from<VER>(F, c, cold, x, y, out);
+        for (int i = 0; i < 16; ++i) f[i] = ring[s0][i][c0];
+        NbrVel nv;
+        nv.ux_xp = ring[s0][16][c0 + 1];
+        nv.uy_xp = ring[s0][17][c0 + 1];
+        nv.ux_xm = ring[s0][16][c0 - 1];
+        nv.uy_xm = ring[s0][17][c0 - 1];
+        nv.ux_yp = ring[sp][16][c0];
+        nv.uy_yp = ring[sp][17][c0];
+        nv.ux_ym = ring[sm][16][c0];
+        nv.uy_ym = ring[sm][17][c0];
+        ok &= collide_add<VER>(c, f, nv, out) || x >= F.nx;
+        store_node_stream(F, x, y, out);
+        if (WALLS) walls_from<VER>(F, c, cold, x, y, out);
+      }
     }
     __syncthreads();
     const int yn = Y + WAVES + 1 + w;
-    if (yn <= y1) {
+    if (FULL || yn <= y1) {
       fix_ghost(cold, sx, ysrc(yn), cur);
-      to_ring((yn - base) % RING, cur);
+      to_ring((yn - base) % RING, cur, ecur);
     }
   };
-  for (int Y = y0; Y < y1; Y += 2 * WAVES) {
-    iteration(Y, fa, fb);
+  using Full = std::integral_constant<bool, true>;
+  using Part = std::integral_constant<bool, false>;
+  int Y = y0;
+  for (; Y + 3 * WAVES <= y1; Y += 2 * WAVES) {
+    iteration(Full{}, Y, fa, ea, fb, eb);
+    iteration(Full{}, Y + WAVES, fb, eb, fa, ea);
+  }
+  for (; Y < y1; Y += 2 * WAVES) {
+    iteration(Part{}, Y, fa, ea, fb, eb);
     if (Y + WAVES >= y1) break;
-    iteration(Y + WAVES, fb, fa);
+    iteration(Part{}, Y + WAVES, fb, eb, fa, ea);
   }
   if (!ok) flag[0] = 1;
+}
+
+// ---------------------------------------------------------------------------
+// Streaming probe: copies 16 pitched planes with the fused kernel's access
+// pattern (64-column strips, WAVES wavefronts on consecutive rows, the next
+// row in flight, non-temporal stores) and no arithmetic; its bandwidth is
+// what a kernel with this access pattern can reach.
+// ---------------------------------------------------------------------------
+// (template only so that every translation unit gets its own instance)
+template <int U>
+__global__ __launch_bounds__(64 * WAVES) void k_stream_copy(const double* __restrict__ src, double* __restrict__ dst,
+                                                            int ny, long long pitch, int rows, int nstrips,
+                                                            int ntiles) {
+  const int tile = blockIdx.x;
+  if (tile >= ntiles) return;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int strip = tile % nstrips, seg = tile / nstrips;
+  const int y0 = seg * rows, y1 = min(y0 + rows, ny);
+  const long long plane = (long long)ny * pitch;
+  const int x = strip * STRIP + lane;
+  double a[16], b[16];
+  auto load = [&](int y, double* v) {
+    const double* p = src + (long long)y * pitch + x;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = p[i * plane];
+  };
+  auto store = [&](int y, const double* v) {
+    double* q = dst + (long long)y * pitch + x;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) __builtin_nontemporal_store(v[i], q + i * plane);
+  };
+  load(min(y0 + w, y1 - 1), a);
+  for (int y = y0 + w; y < y1; y += 2 * WAVES) {
+    load(min(y + WAVES, y1 - 1), b);
+    store(y, a);
+    if (y + WAVES >= y1) break;
+    load(min(y + 2 * WAVES, y1 - 1), a);
+    store(y + WAVES, b);
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -84,6 +84,7 @@ def load():
             "lbm_get_tile": ([P, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
             "lbm_last_error": ([], ctypes.c_char_p),
             "lbm_destroy": ([P], None),
+            "lbm_stream_copy": ([P, P, ctypes.c_int32, ctypes.c_int32, P], ctypes.c_int),
         }
         for name, (args, res) in sigs.items():
             fn = getattr(lib, name)
@@ -184,6 +185,15 @@ def lbm_get_tile(h):
 
 def lbm_destroy(h):
     load().lbm_destroy(h)
+
+
+def lbm_stream_copy(src, dst, nx, ny):
+    """Diagnostic copy of 16 pitched planes with the step kernel's access
+    pattern (src, dst: float64 device tensors of 16 * ny * pitch doubles)."""
+    pitch = (int(nx) + 63) // 64 * 64
+    n = 16 * int(ny) * pitch
+    assert src.numel() >= n and dst.numel() >= n, "buffers need 16 * ny * pitch doubles"
+    _check(load().lbm_stream_copy(_ptr(src), _ptr(dst), int(nx), int(ny), _stream()))
 
 
 # ---------------------------------------------------------------------------
