@@ -74,7 +74,7 @@ def run_problem(p, fields, steps, warmup, rows=None, tune=False):
     out = {"seconds": t, "steps": steps, "nodes": nodes, "mlups": nodes * steps / t / 1e6,
            "ms_per_step": 1e3 * t / steps, "gbps": nodes * steps * BYTES_PER_NODE / t / 1e9}
     if tuned:
-        out["tile_rows"] = tuned[0]
+        out["tile_rows"], out["tile_waves"] = tuned[0], tuned[1]
     return out
 
 
@@ -288,7 +288,8 @@ def main():
     achieved = bytes_per_launch / (head["seconds"] / head["steps"]) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                 "frac": round(achieved * 1e9 / HBM_PEAK, 4), "traffic": traffic_from_profiles(kernel, workload),
-                "kernel": kernel, "algorithmic_bytes_per_launch": bytes_per_launch}
+                "kernel": kernel, "algorithmic_bytes_per_launch": bytes_per_launch,
+                "tile_rows": head.get("tile_rows"), "tile_waves": head.get("tile_waves")}
     out = {
         "metric": "MLUPS (FP64 node updates/s) and fraction of HBM roofline",
         "value": round(head["mlups"], 1),

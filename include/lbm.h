@@ -125,19 +125,22 @@ lbm_status lbm_check(lbm_handle* h);
 
 /* Kernel variant used by lbm_step: 0 = the fused LDS-staged kernel (default),
  * 1 = the plain one-thread-per-node global-memory kernel (a reference for
- * race and indexing checks). lbm_set_tile sets the rows per workgroup tile
- * of variant 0 (1..1024, rounded up to a multiple of 4; results do not
- * depend on it). */
+ * race and indexing checks). lbm_set_tile sets the tile shape of variant 0:
+ * rows per workgroup tile (1..1024, rounded up to a multiple of waves) and
+ * wavefronts per workgroup (2 or 4; problems with NEQ walls always use 4).
+ * Results do not depend on the tile shape. */
 lbm_status lbm_set_variant(lbm_handle* h, int32_t variant);
-lbm_status lbm_set_tile(lbm_handle* h, int32_t rows);
+lbm_status lbm_set_tile(lbm_handle* h, int32_t rows, int32_t waves);
 
-/* Tile-height tuner for variant 0: times probe_steps steps for each
- * candidate tile height (synchronising the stream) and keeps the fastest
- * (*rows_out, *best_ms may be NULL). With d_scratch (device, >= 16 ny pitch
- * doubles) the state is saved and restored; with NULL the state advances. */
+/* Tile-shape tuner for variant 0: times probe_steps steps for each
+ * candidate (wavefronts per workgroup x tile height), synchronising the
+ * stream, and keeps the fastest (rows_out, waves_out, best_ms may be NULL).
+ * With d_scratch (device, >= 16 ny pitch doubles) the state is saved and
+ * restored; with NULL the state advances. */
 lbm_status lbm_tune(lbm_handle* h, int64_t probe_steps, double* d_scratch, size_t scratch_bytes, int32_t* rows_out,
-                    double* best_ms);
-lbm_status lbm_get_tile(const lbm_handle* h, int32_t* rows);
+                    int32_t* waves_out, double* best_ms);
+/* Current tile shape (either pointer may be NULL). */
+lbm_status lbm_get_tile(const lbm_handle* h, int32_t* rows, int32_t* waves);
 
 /* Diagnostic, not part of the method: copies the 16 pitched planes of an
  * nx-by-ny field laid out like the distributions ([16][ny][pitch], pitch = nx

@@ -25,7 +25,7 @@ extern "C" {
 typedef struct lbm_adjoint lbm_adjoint;
 
 /* Device workspace for p, nsteps and a checkpoint interval (0 = round(sqrt(nsteps))):
- * checkpoints, segment store, two adjoint buffers, per-node records, the
+ * checkpoints, segment store, two adjoint buffers, two per-node record buffers, the
  * s-gradient partials and constants; 0 if invalid (also for NEQ walls). */
 size_t lbm_adjoint_workspace_bytes(const lbm_params* p, int64_t nsteps, int32_t ckpt_interval);
 

@@ -50,7 +50,7 @@ lbm_status adj_layout(const lbm_params* p, int64_t nsteps, int32_t ckpt, AdjLayo
   L->lam = off;
   off += 2 * state;
   L->rec = off;
-  off += a256((size_t)NREC * L->plane * sizeof(double));
+  off += 2 * a256((size_t)NREC * L->plane * sizeof(double));
   L->partials = off;
   off += a256((size_t)L->gx * L->gy * 12 * sizeof(double));
   L->flag = off;
@@ -77,7 +77,9 @@ struct lbm_adjoint {
   const Hot* dhot() { return &((Consts*)(base + L.consts))->hot; }
   const Cold* dcold() { return &((Consts*)(base + L.consts))->cold; }
   const AdjCoef* dadj() { return (const AdjCoef*)(base + L.adj); }
-  double* rec() { return (double*)(base + L.rec); }
+  double* rec(int j) {
+    return (double*)(base + L.rec + (size_t)j * a256((size_t)NREC * L.plane * sizeof(double)));
+  }
   double* partials() { return (double*)(base + L.partials); }
   int* flag() { return (int*)(base + L.flag); }
   Field field(const double* fin, double* fout) {
@@ -94,7 +96,7 @@ struct lbm_adjoint {
 
 static hipError_t step_into(lbm_adjoint* a, const double* fin, double* fout) {
   return launch_step(a->field(fin, fout), a->dhot(), a->dcold(), a->p.eq_version, false, 0,
-                     default_rows(a->p.nx, a->p.ny), a->flag(), a->stream);
+                     default_tile(a->p.nx, a->p.ny), a->flag(), a->stream);
 }
 
 extern "C" {
@@ -199,7 +201,7 @@ lbm_status lbm_adjoint_backward(lbm_adjoint* a, const double* d_rho0, const doub
   const AdjLayout& L = a->L;
   const dim3 grow((a->p.nx + 63) / 64, a->p.ny);
   const dim3 gblk(L.gx, L.gy), bblk(64, 4);
-  int cur = 0;
+  int cur = 0, rc = 0;
   // lambda^T from the gradients of the final fields
   hipLaunchKernelGGL(k_adj_final<0>, grow, dim3(64), 0, a->stream, a->field(a->ckpt(L.K), nullptr), d_g_rho, d_g_ux,
                      d_g_uy, d_g_T, a->lam(cur));
@@ -217,15 +219,21 @@ lbm_status lbm_adjoint_backward(lbm_adjoint* a, const double* d_rho0, const doub
       e = step_into(a, fin, a->seg((int)(n - n0)));
       if (e != hipSuccess) return hip_fail(e, "recompute step launch");
     }
+    // Each adjoint step n needs the records (dL/dA, dL/dB, velocity) of
+    // every node at level n; step n writes those of step n - 1 as it
+    // produces lambda^n, except across a segment boundary, where level
+    // n - 1 is not recomputed yet and a records pass runs first.
     for (int64_t n = n1 - 1; n >= n0; --n) {
       const double* fn = (n == n0) ? a->ckpt(k) : a->seg((int)(n - n0));
+      const double* fprev = (n - 1 < n0) ? nullptr : (n - 1 == n0) ? a->ckpt(k) : a->seg((int)(n - 1 - n0));
       Field F = a->field(fn, nullptr);
-      hipLaunchKernelGGL(krec, gblk, bblk, 0, a->stream, F, a->lam(cur), a->rec(), a->dhot());
-      hipLaunchKernelGGL(kstep, gblk, bblk, 0, a->stream, F, a->lam(cur), a->lam(cur ^ 1), a->rec(), a->dhot(),
-                         a->dcold(), a->dadj(), a->partials());
+      if (n == n1 - 1) hipLaunchKernelGGL(krec, gblk, bblk, 0, a->stream, F, a->lam(cur), a->rec(rc), a->dhot());
+      hipLaunchKernelGGL(kstep, gblk, bblk, 0, a->stream, F, a->lam(cur), a->lam(cur ^ 1), a->rec(rc), a->dhot(),
+                         a->dcold(), a->dadj(), a->partials(), fprev, a->rec(rc ^ 1));
       e = hipGetLastError();
       if (e != hipSuccess) return hip_fail(e, "adjoint step launch");
       cur ^= 1;
+      if (fprev) rc ^= 1;
     }
   }
   // initial-state adjoint and the s-gradient

@@ -40,15 +40,9 @@ struct AdjCoef {
 // Per-node record written by the first pass: dL/dA, dL/dB and the velocity.
 enum { REC_GA = 0, REC_GB = 1, REC_UX = 2, REC_UY = 3, NREC = 4 };
 
-LBM_HD void adj_record(const Field& F, const Hot& c, const double* __restrict__ lam, double* __restrict__ rec, int x,
-                       int y) {
-  const long long k = (long long)y * F.pitch + x;
-  double f[16], l[16];
-#pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    f[i] = F.fin[k + i * F.plane];
-    l[i] = lam[k + i * F.plane];
-  }
+// Record of a node from its distributions f (the forward level the next
+// adjoint step linearises about) and its lambda (that step's input).
+LBM_HD void record_from(const Hot& c, const double* f, const double* l, double* r) {
   double m[16], mu[16];
   moments_from_f(f, m);
   minvt_apply(l, mu);
@@ -58,10 +52,24 @@ LBM_HD void adj_record(const Field& F, const Hot& c, const double* __restrict__ 
   const double rT = rho * T;
   double vx, vy;
   velocity_of(f, vx, vy);
-  rec[k + REC_GA * F.plane] = mu[6] * c.cmod[0] * rT * ux + mu[7] * c.cmod[3] * rT * uy;
-  rec[k + REC_GB * F.plane] = mu[6] * c.cmod[1] * rT * uy + mu[7] * c.cmod[2] * rT * ux;
-  rec[k + REC_UX * F.plane] = vx;
-  rec[k + REC_UY * F.plane] = vy;
+  r[REC_GA] = mu[6] * c.cmod[0] * rT * ux + mu[7] * c.cmod[3] * rT * uy;
+  r[REC_GB] = mu[6] * c.cmod[1] * rT * uy + mu[7] * c.cmod[2] * rT * ux;
+  r[REC_UX] = vx;
+  r[REC_UY] = vy;
+}
+
+LBM_HD void adj_record(const Field& F, const Hot& c, const double* __restrict__ lam, double* __restrict__ rec, int x,
+                       int y) {
+  const long long k = (long long)y * F.pitch + x;
+  double f[16], l[16], r[NREC];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    f[i] = F.fin[k + i * F.plane];
+    l[i] = lam[k + i * F.plane];
+  }
+  record_from(c, f, l, r);
+#pragma unroll
+  for (int j = 0; j < NREC; ++j) rec[k + j * F.plane] = r[j];
 }
 
 template <int VER>
@@ -158,10 +166,12 @@ LBM_HD double conv_t_axis(int v, const double* lc, double lo, double hi, double 
 
 // New adjoint lambda^n at node (x, y) into lam_out; adds this node's
 // contribution to dL/ds_5..16 (index k - 5) into sg.
+// With f_prev (the forward level of the next adjoint step, same layout as
+// F.fin) also writes that step's record of this node into rec_out.
 template <int VER>
 LBM_HD void adj_node(const Field& F, const Hot& c, const Cold* __restrict__ cold, const AdjCoef* __restrict__ adj,
                      const double* __restrict__ lam_in, double* __restrict__ lam_out, const double* __restrict__ rec,
-                     int x, int y, double* sg) {
+                     const double* __restrict__ f_prev, double* __restrict__ rec_out, int x, int y, double* sg) {
   const long long k0 = (long long)y * F.pitch + x;
   double f[16], l[16];
 #pragma unroll
@@ -246,6 +256,14 @@ LBM_HD void adj_node(const Field& F, const Hot& c, const Cold* __restrict__ cold
   }
 #pragma unroll
   for (int i = 0; i < 16; ++i) lam_out[k0 + i * F.plane] = out[i];
+  if (f_prev) {
+    double fp[16], r[NREC];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) fp[i] = f_prev[k0 + i * F.plane];
+    record_from(c, fp, out, r);
+#pragma unroll
+    for (int j = 0; j < NREC; ++j) rec_out[k0 + j * F.plane] = r[j];
+  }
   // --- dL/ds: d col_k/d s_k = -dt (m_k - q_k), plus the modification's
   // coefficients (their s-derivatives already carry the factor dt)
 #pragma unroll
@@ -277,7 +295,8 @@ template <int VER>
 __global__ __launch_bounds__(256) void k_adj_step(Field F, const double* __restrict__ lam_in,
                                                   double* __restrict__ lam_out, const double* __restrict__ rec,
                                                   const Hot* __restrict__ hot, const Cold* __restrict__ cold,
-                                                  const AdjCoef* __restrict__ adj, double* __restrict__ partials) {
+                                                  const AdjCoef* __restrict__ adj, double* __restrict__ partials,
+                                                  const double* __restrict__ f_prev, double* __restrict__ rec_out) {
   __shared__ Hot hs;
   __shared__ double red[12][4];
   stage_hot(hot, &hs);
@@ -287,7 +306,7 @@ __global__ __launch_bounds__(256) void k_adj_step(Field F, const double* __restr
   double sg[12];
 #pragma unroll
   for (int k = 0; k < 12; ++k) sg[k] = 0.0;
-  if (x < F.nx && y < F.ny) adj_node<VER>(F, hs, cold, adj, lam_in, lam_out, rec, x, y, sg);
+  if (x < F.nx && y < F.ny) adj_node<VER>(F, hs, cold, adj, lam_in, lam_out, rec, f_prev, rec_out, x, y, sg);
   // deterministic block reduction, one slot per block, accumulated over steps
 #pragma unroll
   for (int k = 0; k < 12; ++k) {

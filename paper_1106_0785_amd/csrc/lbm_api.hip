@@ -115,11 +115,12 @@ void make_coef(const lbm_params* p, Hot* c, Cold* cold) {
   c->modified = p->modified;
 }
 
-MarchGeom march_geom(int nx, int ny, int rows) {
+MarchGeom march_geom(int nx, int ny, TileShape t) {
   MarchGeom g;
+  const int w = t.waves;
   g.nstrips = (nx + STRIP - 1) / STRIP;
-  rows = std::max(WAVES, std::min(rows, (ny + WAVES - 1) / WAVES * WAVES));
-  g.rows = (rows + WAVES - 1) / WAVES * WAVES;
+  int rows = std::max(w, std::min(t.rows, (ny + w - 1) / w * w));
+  g.rows = (rows + w - 1) / w * w;
   g.nsegs = (ny + g.rows - 1) / g.rows;
   g.ntiles = g.nstrips * g.nsegs;
   g.per_xcd = (g.ntiles + 7) / 8;
@@ -127,30 +128,33 @@ MarchGeom march_geom(int nx, int ny, int rows) {
 }
 
 hipError_t launch_step(const Field& F, const Hot* c, const Cold* cold, int version, bool walls, int variant,
-                       int rows, int* flag, hipStream_t s) {
+                       TileShape t, int* flag, hipStream_t s) {
   if (variant == 1) {
     dim3 block(64, 4);
     dim3 grid((F.nx + 63) / 64, (F.ny + 3) / 4);
     auto k = version == 2 ? k_step_plain<2> : version == 3 ? k_step_plain<3> : k_step_plain<1>;
     hipLaunchKernelGGL(k, grid, block, 0, s, F, c, cold, flag);
-  } else {
-    const MarchGeom g = march_geom(F.nx, F.ny, rows);
-    decltype(&k_step_fused<1, false>) k;
-    if (walls)
-      k = version == 2 ? k_step_fused<2, true> : version == 3 ? k_step_fused<3, true> : k_step_fused<1, true>;
-    else
-      k = version == 2 ? k_step_fused<2, false> : version == 3 ? k_step_fused<3, false> : k_step_fused<1, false>;
-    hipLaunchKernelGGL(k, dim3(8 * g.per_xcd), dim3(64 * WAVES), 0, s, F, c, cold, g, flag);
+    return hipGetLastError();
   }
+  if (walls || t.waves != 2) t.waves = 4;
+  const MarchGeom g = march_geom(F.nx, F.ny, t);
+  decltype(&k_step_fused<1, false, 4>) k;
+  if (walls)
+    k = version == 2 ? k_step_fused<2, true, 4> : version == 3 ? k_step_fused<3, true, 4> : k_step_fused<1, true, 4>;
+  else if (t.waves == 2)
+    k = version == 2 ? k_step_fused<2, false, 2> : version == 3 ? k_step_fused<3, false, 2> : k_step_fused<1, false, 2>;
+  else
+    k = version == 2 ? k_step_fused<2, false, 4> : version == 3 ? k_step_fused<3, false, 4> : k_step_fused<1, false, 4>;
+  hipLaunchKernelGGL(k, dim3(8 * g.per_xcd), dim3(64 * t.waves), 0, s, F, c, cold, g, flag);
   return hipGetLastError();
 }
 
-int default_rows(int nx, int ny) {
+TileShape default_tile(int nx, int ny) {
   // tall tiles amortise the two halo rows; keep at least ~2 workgroups per CU
   const long long strips = (nx + STRIP - 1) / STRIP;
   int rows = 64;
   while (rows > WAVES && strips * ((ny + rows - 1) / rows) < 1024) rows /= 2;
-  return rows;
+  return TileShape{rows, WAVES};
 }
 
 }  // namespace lbm
@@ -166,7 +170,7 @@ struct lbm_handle {
   int* flag;
   long long pitch, plane;
   int variant;
-  int rows;
+  TileShape tile;
 };
 
 static Field field_of(const lbm_handle* h, int from) {
@@ -217,7 +221,7 @@ lbm_status lbm_create(const lbm_params* p, void* d_workspace, size_t ws_bytes, v
   h->dev = (Consts*)(base + 2 * 16 * h->plane * sizeof(double) + 256);
   h->cur = 0;
   h->variant = 0;
-  h->rows = default_rows(p->nx, p->ny);
+  h->tile = default_tile(p->nx, p->ny);
   e = hipMemsetAsync(h->flag, 0, 256, h->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(h->dev, &h->host, sizeof(Consts), hipMemcpyHostToDevice, h->stream);
@@ -253,7 +257,7 @@ lbm_status lbm_step(lbm_handle* h, int64_t nsteps) {
   for (int64_t n = 0; n < nsteps; ++n) {
     hipError_t e =
         launch_step(field_of(h, h->cur), &h->dev->hot, &h->dev->cold, h->p.eq_version, has_walls(&h->p), h->variant,
-                    h->rows, h->flag, h->stream);
+                    h->tile, h->flag, h->stream);
     if (e != hipSuccess) return hip_fail(e, "step kernel launch");
     h->cur ^= 1;
   }
@@ -310,15 +314,16 @@ lbm_status lbm_set_variant(lbm_handle* h, int32_t variant) {
   return LBM_OK;
 }
 
-lbm_status lbm_set_tile(lbm_handle* h, int32_t rows) {
+lbm_status lbm_set_tile(lbm_handle* h, int32_t rows, int32_t waves) {
   if (!h) return fail(LBM_EINVAL, "handle is NULL");
   if (rows < 1 || rows > 1024) return fail(LBM_EINVAL, "rows must be in 1..1024");
-  h->rows = rows;
+  if (waves != 2 && waves != 4) return fail(LBM_EINVAL, "waves must be 2 or 4");
+  h->tile = TileShape{rows, has_walls(&h->p) ? 4 : waves};
   return LBM_OK;
 }
 
 lbm_status lbm_tune(lbm_handle* h, int64_t probe_steps, double* d_scratch, size_t scratch_bytes, int32_t* rows_out,
-                    double* best_ms) {
+                    int32_t* waves_out, double* best_ms) {
   if (!h) return fail(LBM_EINVAL, "handle is NULL");
   if (probe_steps < 1) return fail(LBM_EINVAL, "probe_steps must be >= 1");
   const size_t state = 16 * (size_t)h->plane * sizeof(double);
@@ -336,48 +341,59 @@ lbm_status lbm_tune(lbm_handle* h, int64_t probe_steps, double* d_scratch, size_
     h->variant = saved_variant;
     return hip_fail(e, "hipEventCreate");
   }
-  const int cand[] = {4, 8, 12, 16, 20, 24, 28, 32, 40, 48, 56, 64, 96, 128};
-  int best = h->rows, last_rows = -1;
+  const int cand[] = {4, 8, 12, 16, 20, 24, 28, 32, 40, 48, 56, 64, 96, 128, 192, 256};
+  const int wcand[] = {4, 2};
+  TileShape best = h->tile;
   float best_t = 1e30f;
-  for (int r : cand) {
-    const MarchGeom g = march_geom(h->p.nx, h->p.ny, r);
-    if (g.rows == last_rows) continue;  // same tiling as a smaller candidate
-    last_rows = g.rows;
-    h->rows = g.rows;
-    lbm_status st = lbm_step(h, 2);  // warm-up
-    if (st != LBM_OK) break;
-    e = hipEventRecord(t0, h->stream);
-    if (e == hipSuccess) st = lbm_step(h, probe_steps);
-    if (e == hipSuccess) e = hipEventRecord(t1, h->stream);
-    if (e == hipSuccess) e = hipEventSynchronize(t1);
-    if (e != hipSuccess || st != LBM_OK) break;
-    float ms = 0;
-    e = hipEventElapsedTime(&ms, t0, t1);
-    if (e != hipSuccess) break;
-    if (ms < best_t) {
-      best_t = ms;
-      best = g.rows;
+  lbm_status st = LBM_OK;
+  for (int wv : wcand) {
+    if (wv != 4 && has_walls(&h->p)) continue;
+    int last_rows = -1;
+    for (int r : cand) {
+      const TileShape t{r, wv};
+      const MarchGeom g = march_geom(h->p.nx, h->p.ny, t);
+      if (g.rows == last_rows) continue;  // same tiling as a smaller candidate
+      last_rows = g.rows;
+      h->tile = TileShape{g.rows, wv};
+      st = lbm_step(h, 2);  // warm-up
+      if (st != LBM_OK) break;
+      e = hipEventRecord(t0, h->stream);
+      if (e == hipSuccess) st = lbm_step(h, probe_steps);
+      if (e == hipSuccess) e = hipEventRecord(t1, h->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(t1);
+      if (e != hipSuccess || st != LBM_OK) break;
+      float ms = 0;
+      e = hipEventElapsedTime(&ms, t0, t1);
+      if (e != hipSuccess) break;
+      if (ms < best_t) {
+        best_t = ms;
+        best = h->tile;
+      }
     }
+    if (e != hipSuccess || st != LBM_OK) break;
   }
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
   h->variant = saved_variant;
-  h->rows = best;
+  h->tile = best;
   if (e != hipSuccess) return hip_fail(e, "tuning run");
+  if (st != LBM_OK) return st;
   if (d_scratch) {
     h->cur = saved_cur;
     e = hipMemcpyAsync(h->f[h->cur], d_scratch, state, hipMemcpyDeviceToDevice, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_fail(e, "restoring the state");
   }
-  if (rows_out) *rows_out = best;
+  if (rows_out) *rows_out = best.rows;
+  if (waves_out) *waves_out = best.waves;
   if (best_ms) *best_ms = best_t;
   return LBM_OK;
 }
 
-lbm_status lbm_get_tile(const lbm_handle* h, int32_t* rows) {
-  if (!h || !rows) return fail(LBM_EINVAL, "NULL argument");
-  *rows = h->rows;
+lbm_status lbm_get_tile(const lbm_handle* h, int32_t* rows, int32_t* waves) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (rows) *rows = h->tile.rows;
+  if (waves) *waves = h->tile.waves;
   return LBM_OK;
 }
 

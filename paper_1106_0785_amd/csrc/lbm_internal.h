@@ -22,10 +22,16 @@ struct Consts {
 
 size_t consts_bytes();
 void make_coef(const lbm_params* p, Hot* c, Cold* cold);
-MarchGeom march_geom(int nx, int ny, int rows);
+// Tile shape of the fused step kernel: rows per tile and wavefronts per
+// workgroup (2 or 4; problems with NEQ walls always use 4).
+struct TileShape {
+  int rows;
+  int waves;
+};
+MarchGeom march_geom(int nx, int ny, TileShape t);
 bool has_walls(const lbm_params* p);
 hipError_t launch_step(const Field& F, const Hot* c, const Cold* cold, int version, bool walls, int variant,
-                       int rows, int* flag, hipStream_t s);
-int default_rows(int nx, int ny);
+                       TileShape t, int* flag, hipStream_t s);
+TileShape default_tile(int nx, int ny);
 
 }  // namespace lbm

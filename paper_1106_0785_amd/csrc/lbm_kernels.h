@@ -184,9 +184,9 @@ __global__ __launch_bounds__(256) void k_step_plain(Field F, const Hot* __restri
 }
 
 // ---------------------------------------------------------------------------
-// Fused kernel. A workgroup of WAVES wavefronts owns a tile of STRIP = 64
-// columns (one per lane, 512-byte aligned rows) by `rows` rows and marches up
-// it WAVES rows at a time. Rows y-1 .. y+WAVES live in a ring of RING rows in
+// Fused kernel. A workgroup of W wavefronts (2 or 4) owns a tile of STRIP =
+// 64 columns (one per lane, 512-byte aligned rows) by `rows` rows and marches
+// up it W rows at a time. Rows y-1 .. y+W live in a ring of W + 2 rows in
 // LDS, each RW = 66 entries wide: the left neighbour column x0-1, the 64
 // strip columns, the right neighbour column x0+64, with 16 distributions and
 // the velocity per entry. Each distribution is read from HBM about once and
@@ -198,9 +198,8 @@ __global__ __launch_bounds__(256) void k_step_plain(Field F, const Hot* __restri
 // 16 lanes of a DPP row.
 // ---------------------------------------------------------------------------
 constexpr int STRIP = 64;
-constexpr int WAVES = 4;
-constexpr int RING = WAVES + 2;
-constexpr int NV = 18;  // 16 distributions + u_x + u_y per ring entry
+constexpr int WAVES = 4;  // wavefronts per workgroup of the default tile shape
+constexpr int NV = 18;    // 16 distributions + u_x + u_y per ring entry
 constexpr int RW = STRIP + 2;
 
 // Convection of all 16 velocities with the stencil values read from the LDS
@@ -249,7 +248,7 @@ __device__ __forceinline__ int lane_table(const int (&t)[16], int i) {
 
 struct MarchGeom {
   int nstrips;  // ceil(nx / STRIP)
-  int rows;     // rows per tile (multiple of WAVES)
+  int rows;     // rows per tile (multiple of the workgroup's wavefront count)
   int nsegs;    // ceil(ny / rows)
   int ntiles;   // nstrips * nsegs
   int per_xcd;  // ceil(ntiles / 8)
@@ -260,9 +259,12 @@ struct MarchGeom {
 // same L2.
 __device__ __forceinline__ int xcd_tile(int b, const MarchGeom& g) { return (b % 8) * g.per_xcd + b / 8; }
 
-template <int VER, bool WALLS>
-__global__ __launch_bounds__(64 * WAVES, 2) void k_step_fused(Field F, const Hot* __restrict__ hot,
-                                                               const Cold* __restrict__ cold, MarchGeom g, int* flag) {
+// W wavefronts per workgroup (2 or 4); the ring holds RING = W + 2 rows.
+template <int VER, bool WALLS, int W>
+__global__ __launch_bounds__(64 * W, 2) void k_step_fused(Field F, const Hot* __restrict__ hot,
+                                                           const Cold* __restrict__ cold, MarchGeom g, int* flag) {
+  constexpr int WAVES = W;
+  constexpr int RING = W + 2;
   __shared__ double ring[RING][NV][RW];
   __shared__ Hot hs;
   const int tile = xcd_tile(blockIdx.x, g);
@@ -327,15 +329,21 @@ __global__ __launch_bounds__(64 * WAVES, 2) void k_step_fused(Field F, const Hot
     ring[slot][17][ecol] = ejy * ir;
   };
 
-  // prologue: rows y0-1 .. y0+WAVES (only those <= y1 are ever read)
-  for (int r = w; r < RING; r += WAVES) {
-    const int yr = base + r;
-    if (yr <= y1) {
-      const Src sy = ysrc(yr);
-      double f[16];
-      load_point(F, cold, sx, sy, f);
-      const double e = eptr[sy.idx * estride];
-      to_ring(r, f, e);
+  // Prologue: ring rows y0-1 .. y0+W (only those <= y1 are ever read);
+  // wave w fills slots w and w + W (< RING). Every load of the prologue
+  // and of the first prefetch row is issued before any of them is used.
+  static_assert(RING - WAVES <= WAVES, "each wave fills at most two prologue slots");
+  const bool two = w < RING - WAVES;
+  const int ya = min(base + w, y1), yb = min(base + w + WAVES, y1);
+  double pa[16], pb[16], pea, peb = 0.0;
+  {
+    const int ia = ysrc(ya).idx;
+    load_raw(F, sx.idx, ia, pa);
+    pea = eptr[ia * estride];
+    if (two) {
+      const int ib = ysrc(yb).idx;
+      load_raw(F, sx.idx, ib, pb);
+      peb = eptr[ib * estride];
     }
   }
 
@@ -352,6 +360,14 @@ __global__ __launch_bounds__(64 * WAVES, 2) void k_step_fused(Field F, const Hot
     const int yi = ysrc(yn).idx;
     load_raw(F, sx.idx, yi, fa);
     ea = eptr[yi * estride];
+  }
+  if (base + w <= y1) {
+    fix_ghost(cold, sx, ysrc(base + w), pa);
+    to_ring(w, pa, pea);
+  }
+  if (two && base + w + WAVES <= y1) {
+    fix_ghost(cold, sx, ysrc(base + w + WAVES), pb);
+    to_ring(w + WAVES, pb, peb);
   }
   bool ok = true;
   auto iteration = [&](auto full, int Y, double* cur, double& ecur, double* nxt, double& enxt) {

@@ -78,10 +78,10 @@ def load():
             "lbm_set_f": ([P, P], ctypes.c_int),
             "lbm_check": ([P], ctypes.c_int),
             "lbm_set_variant": ([P, ctypes.c_int32], ctypes.c_int),
-            "lbm_set_tile": ([P, ctypes.c_int32], ctypes.c_int),
+            "lbm_set_tile": ([P, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
             "lbm_tune": ([P, ctypes.c_int64, P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int32),
-                          ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
-            "lbm_get_tile": ([P, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+                          ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+            "lbm_get_tile": ([P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
             "lbm_last_error": ([], ctypes.c_char_p),
             "lbm_destroy": ([P], None),
             "lbm_stream_copy": ([P, P, ctypes.c_int32, ctypes.c_int32, P], ctypes.c_int),
@@ -164,23 +164,28 @@ def lbm_set_variant(h, variant):
     _check(load().lbm_set_variant(h, int(variant)))
 
 
-def lbm_set_tile(h, rows):
-    _check(load().lbm_set_tile(h, int(rows)))
+def lbm_set_tile(h, rows, waves=4):
+    _check(load().lbm_set_tile(h, int(rows), int(waves)))
 
 
 def lbm_tune(h, probe_steps, scratch=None):
+    """Returns (rows, waves, best_ms)."""
     rows = ctypes.c_int32()
+    waves = ctypes.c_int32()
     ms = ctypes.c_double()
     sp = ctypes.c_void_p(scratch.data_ptr()) if scratch is not None else None
     nbytes = scratch.numel() * scratch.element_size() if scratch is not None else 0
-    _check(load().lbm_tune(h, int(probe_steps), sp, nbytes, ctypes.byref(rows), ctypes.byref(ms)))
-    return rows.value, ms.value
+    _check(load().lbm_tune(h, int(probe_steps), sp, nbytes, ctypes.byref(rows), ctypes.byref(waves),
+                           ctypes.byref(ms)))
+    return rows.value, waves.value, ms.value
 
 
 def lbm_get_tile(h):
+    """Returns (rows, waves)."""
     rows = ctypes.c_int32()
-    _check(load().lbm_get_tile(h, ctypes.byref(rows)))
-    return rows.value
+    waves = ctypes.c_int32()
+    _check(load().lbm_get_tile(h, ctypes.byref(rows), ctypes.byref(waves)))
+    return rows.value, waves.value
 
 
 def lbm_destroy(h):
@@ -256,15 +261,16 @@ class Simulation:
     def set_variant(self, v):
         lbm_set_variant(self.handle, v)
 
-    def set_tile(self, rows):
-        lbm_set_tile(self.handle, rows)
+    def set_tile(self, rows, waves=4):
+        lbm_set_tile(self.handle, rows, waves)
 
     def tile(self):
         return lbm_get_tile(self.handle)
 
     def tune(self, probe_steps=20, keep_state=True):
-        """Pick the fastest tile height; with keep_state the state is saved
-        to a scratch tensor and restored."""
+        """Pick the fastest tile shape (rows, waves); with keep_state the
+        state is saved to a scratch tensor and restored. Returns (rows,
+        waves, best_ms)."""
         import torch
 
         scratch = None

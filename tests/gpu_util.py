@@ -24,14 +24,14 @@ def log(msg):
     sys.stdout.flush()
 
 
-def gpu_run(p, fields, steps, variant=0, rows=None):
+def gpu_run(p, fields, steps, variant=0, rows=None, waves=4):
     from paper_1106_0785_amd import lbm
 
     sim = lbm.Simulation(p)
     if variant:
         sim.set_variant(variant)
-    if rows:
-        sim.set_tile(rows)
+    if rows or waves != 4:
+        sim.set_tile(rows or 16, waves)
     sim.init(**fields)
     sim.step(steps)
     out = {k: v.cpu().numpy() for k, v in sim.moments().items()}

@@ -66,13 +66,14 @@ def test_fused_matches_plain_kernel():
     assert d <= 1e-13
 
 
-@pytest.mark.parametrize("rows", [4, 8, 16, 64])
-def test_tile_rows_do_not_change_result(rows):
-    """Tile height changes only which workgroup computes a node: bitwise equal."""
+@pytest.mark.parametrize("rows,waves", [(4, 4), (8, 4), (16, 4), (64, 4), (2, 2), (6, 2), (16, 2), (64, 2)])
+def test_tile_shape_does_not_change_result(rows, waves):
+    """The tile shape changes only which workgroup computes a node: bitwise
+    equal results."""
     p, fl, _ = inputs.rm(seed=3, nx=190, ny=77)
-    _, f = gpu_run(p, fl, 30, rows=rows)
-    _, ref = gpu_run(p, fl, 30, rows=4)
-    log("tile rows %d 190x77: bitwise equal to rows 4: %s" % (rows, np.array_equal(f, ref)))
+    _, f = gpu_run(p, fl, 30, rows=rows, waves=waves)
+    _, ref = gpu_run(p, fl, 30, rows=4, waves=4)
+    log("tile %d rows x %d waves 190x77: bitwise equal to 4 x 4: %s" % (rows, waves, np.array_equal(f, ref)))
     assert np.array_equal(f, ref)
 
 
@@ -123,21 +124,23 @@ CASES = {
 }
 
 
+@pytest.mark.parametrize("waves", [4, 2])
 @pytest.mark.parametrize("name", sorted(CASES))
-def test_boundary_and_model_variants(name):
+def test_boundary_and_model_variants(name, waves):
     bc, kw = CASES[name]
     p, fl = _small(7, 70, 23, bc, **kw)
-    log("variant %s 70x23 200 steps" % name)
-    g, _ = gpu_run(p, fl, 200)
+    log("variant %s 70x23 200 steps, %d-wave tiles" % (name, waves))
+    g, _ = gpu_run(p, fl, 200, waves=waves)
     o, _ = oracle_run(p, fl, 200)
     assert_parity(g, o, what=name)
 
 
-def test_dirichlet_ghost():
+@pytest.mark.parametrize("waves", [4, 2])
+def test_dirichlet_ghost(waves):
     p, fl = _small(8, 66, 9, ["dirichlet_eq", "zero_gradient", "periodic", "periodic"])
     p["wall"][0] = [1.05, 0.02, 0.0, 1.02]
-    log("dirichlet x_lo 66x9 200 steps")
-    g, _ = gpu_run(p, fl, 200)
+    log("dirichlet x_lo 66x9 200 steps, %d-wave tiles" % waves)
+    g, _ = gpu_run(p, fl, 200, waves=waves)
     o, _ = oracle_run(p, fl, 200)
     assert_parity(g, o, what="dirichlet")
 
@@ -150,12 +153,13 @@ def test_neq_walls_on_x():
     assert_parity(g, o, what="neq x walls")
 
 
-@pytest.mark.parametrize("shape", [(1, 1), (2, 2), (1, 37), (300, 1), (63, 5), (125, 3)])
-def test_degenerate_shapes(shape):
+@pytest.mark.parametrize("waves", [4, 2])
+@pytest.mark.parametrize("shape", [(1, 1), (2, 2), (1, 37), (300, 1), (63, 5), (125, 3), (64, 7), (129, 6)])
+def test_degenerate_shapes(shape, waves):
     nx, ny = shape
     p, fl = _small(5, nx, ny, ["periodic"] * 4)
-    log("shape %dx%d" % shape)
-    g, _ = gpu_run(p, fl, 100)
+    log("shape %dx%d, %d-wave tiles" % (shape + (waves,)))
+    g, _ = gpu_run(p, fl, 100, waves=waves)
     o, _ = oracle_run(p, fl, 100)
     assert_parity(g, o, what="shape %dx%d" % shape)
 
