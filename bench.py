@@ -78,10 +78,11 @@ def run_problem(p, fields, steps, warmup, rows=None, tune=False):
     return out
 
 
-def bench_batch(steps, seed=0, n=512):
+def bench_batch(steps, seed=0, n=512, plain=True):
     """The 512-instance uneven batch: K steps of the batched form (autotuned
     schedule, graph replays) against the same K steps of the plain path
-    called once per instance (lbm_step on each instance in turn)."""
+    called once per instance (lbm_step on each instance in turn; skipped
+    with plain=False)."""
     import torch
 
     from paper_1106_0785_amd import inputs, lbm
@@ -102,8 +103,31 @@ def bench_batch(steps, seed=0, n=512):
     torch.cuda.synchronize()
     tb = start.elapsed_time(stop) / 1e3
     b.check()
+    # per-instance step budgets (seeded, uniform in [K/4, K]): instances stop at their own budget
+    rng = np.random.default_rng(seed + 1)
+    budgets = [int(v) for v in rng.integers(steps // 4, steps + 1, size=n)]
+    b.init([f for _, _, f in items])
+    b.set_budgets(budgets)
+    b.step(steps)  # warm-up (graph capture)
+    torch.cuda.synchronize()
+    b.init([f for _, _, f in items])
+    start.record()
+    b.step(steps)
+    stop.record()
+    torch.cuda.synchronize()
+    tbb = start.elapsed_time(stop) / 1e3
+    b.check()
+    budget_node_steps = sum(int(p["nx"]) * int(p["ny"]) * k for (_, p, _), k in zip(items, budgets))
     b.close()
 
+    out = {"instances": n, "nodes": nodes, "steps": steps, "batched_seconds": tb,
+           "batched_mlups": nodes * steps / tb / 1e6,
+           "batched_gbps_equivalent": nodes * steps / tb * BYTES_PER_NODE / 1e9,
+           "budgets_seconds": tbb, "budgets_node_steps": budget_node_steps,
+           "budgets_mlups": budget_node_steps / tbb / 1e6,
+           "schedule": {k: sched[k] for k in ("region", "steps_per_launch", "chunks")}}
+    if not plain:
+        return out
     sims = []
     for _, p, f in items:
         s = lbm.Simulation(p)
@@ -121,12 +145,9 @@ def bench_batch(steps, seed=0, n=512):
     for s in sims:
         s.check()
         s.close()
-    mb = nodes * steps / tb / 1e6
     mp = nodes * steps / tp / 1e6
-    return {"instances": n, "nodes": nodes, "steps": steps, "batched_seconds": tb, "plain_seconds": tp,
-            "batched_mlups": mb, "plain_mlups": mp, "batched_over_plain": mb / mp,
-            "batched_gbps_equivalent": mb * 1e6 * BYTES_PER_NODE / 1e9,
-            "schedule": {k: sched[k] for k in ("region", "steps_per_launch", "chunks")}}
+    out.update({"plain_seconds": tp, "plain_mlups": mp, "batched_over_plain": out["batched_mlups"] / mp})
+    return out
 
 
 def bench_adjoint(nx=512, ny=128, steps=2000):
@@ -246,6 +267,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--quick", action="store_true", help="headline workload only")
+    ap.add_argument("--only", choices=["batch", "adjoint"], help="run one side measurement alone and print its JSON "
+                    "(for profiling; not the benchmark line)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X (no multi-GPU path); "
@@ -258,6 +281,12 @@ def main():
 
     lbm.load()
     torch.cuda.set_device(0)
+    if args.only == "batch":
+        print(json.dumps(bench_batch(1000, plain=False)), flush=True)
+        return
+    if args.only == "adjoint":
+        print(json.dumps(bench_adjoint()), flush=True)
+        return
 
     # headline: HBM-resident RM-shaped problem
     nx, ny = 4096, 1024

@@ -191,3 +191,20 @@ def test_health_flag_reports_blow_up():
         sim.check()
     assert e.value.status == -5
     sim.close()
+
+
+@pytest.mark.parametrize("shape", [(4096, 64), (100, 37), (1, 5)])
+def test_stream_copy_probe_copies_exactly(shape):
+    """The bandwidth probe copies every pitched plane (padding included)."""
+    import torch
+
+    from paper_1106_0785_amd import lbm
+
+    nx, ny = shape
+    pitch = (nx + 63) // 64 * 64
+    n = 16 * ny * pitch
+    a = torch.arange(n, dtype=torch.float64, device="cuda") * 0.5 + 1.0
+    b = torch.zeros_like(a)
+    lbm.lbm_stream_copy(a, b, nx, ny)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
