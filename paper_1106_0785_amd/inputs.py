@@ -208,6 +208,44 @@ def rm_fields(nx, ny, a_cells, mach, heavy, x0_cells, shock_cells, width_cells, 
 
 
 # --------------------------------------------------------------------------
+# Shock-bubble interaction (Sec. IV.B(b), Figs. 7-8): a Mach 1.22 shock
+# running in -x through gas at rest (1, 0, 0, p = 1) into a light cylindrical
+# bubble (rho 0.1358, p = 1). Right side: inflow fixed at the post-shock
+# state; left side: extrapolation (zero gradient); y sides: reflecting.
+# --------------------------------------------------------------------------
+def shock_bubble(s5=1e4, s7=1e5, nx=600, ny=100, dx=0.003, dt=1e-5, s_other=1e5, mach=1.22, bubble_rho=0.1358,
+                 radius=None, center=None, shock_x=None, width_cells=3.0, modified=1):
+    """Returns (params, fields, meta). Positions are node indices (0-based):
+    by default the bubble is centred at (0.75 nx - 1, (ny - 1)/2) with radius
+    0.2 ny nodes and the post-shock gas fills the nodes x >= 5 nx / 6; every
+    jump is smoothed with tanh over `width_cells` nodes."""
+    rho2, du, p2, D = post_shock(mach)
+    post = [rho2, -du, 0.0, p2 / rho2]
+    cx, cy = (0.75 * nx - 1.0, 0.5 * (ny - 1)) if center is None else center
+    r0 = 0.2 * ny if radius is None else radius
+    xs = 5.0 * nx / 6.0 - 0.5 if shock_x is None else shock_x
+    x = np.arange(nx, dtype=np.float64)[None, :]
+    y = np.arange(ny, dtype=np.float64)[:, None]
+    w_sh = smooth_step(x, xs, width_cells) + 0.0 * y  # 0 at rest, 1 post-shock
+    r = np.sqrt((x - cx) ** 2 + (y - cy) ** 2)
+    in_b = 1.0 - smooth_step(r, r0, width_cells)  # 1 inside the bubble
+    rho_bg = 1.0 + (rho2 - 1.0) * w_sh
+    pr = 1.0 + (p2 - 1.0) * w_sh
+    rho = rho_bg + (bubble_rho - rho_bg) * in_b
+    ux = -du * w_sh * (1.0 - in_b)
+    T = pr / rho
+    s = rates(s5, s7, s_other)
+    wall = [[1.0, 0.0, 0.0, 1.0] for _ in range(4)]
+    wall[1] = post
+    p = params(nx, ny, dx, dx, dt, s, ["zero_gradient", "dirichlet_eq", "specular", "specular"], wall,
+               modified=modified)
+    fields = {"rho": rho, "ux": ux, "uy": np.zeros_like(rho), "T": T}
+    meta = {"mach": mach, "D": D, "post": post, "bubble_rho": bubble_rho, "radius": r0, "center": (cx, cy),
+            "shock_x": xs, "width_cells": width_cells}
+    return p, fields, meta
+
+
+# --------------------------------------------------------------------------
 # Uneven batch of independent 1-D instances: Riemann problems along x
 # (ny = 1) and thermal Couette columns along y (nx = 1).
 # --------------------------------------------------------------------------

@@ -208,3 +208,14 @@ def test_stream_copy_probe_copies_exactly(shape):
     lbm.lbm_stream_copy(a, b, nx, ny)
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("waves", [4, 2])
+def test_shock_bubble_small(waves):
+    """Shock-bubble set-up (Sec. IV.B(b)) at 120 x 40: fixed-state inflow on
+    the right, extrapolation on the left, reflecting y sides."""
+    p, fl, _ = inputs.shock_bubble(nx=120, ny=40)
+    log("shock-bubble 120x40 2000 steps, %d-wave tiles" % waves)
+    g, _ = gpu_run(p, fl, 2000, waves=waves)
+    o, _ = oracle_run(p, fl, 2000)
+    assert_parity(g, o, what="shock-bubble 120x40")

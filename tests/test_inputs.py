@@ -68,3 +68,27 @@ def test_rm_fields_torch_matches_numpy():
     for k in f:
         assert g[k].device == a.device
         np.testing.assert_allclose(g[k].numpy(), f[k], rtol=0, atol=1e-14)
+
+
+def test_shock_bubble_states_match_paper():
+    """Sec. IV.B(b): the shock-bubble set-up's pre-shock, post-shock and
+    bubble states, the inflow state on the right side and the positions
+    (post-shock region x >= 5/6 of the domain, bubble at 3/4 of the length
+    and mid height)."""
+    g = json.load(open(os.path.join(GOLD, "rm_post_shock.json")))
+    p, f, m = inputs.shock_bubble(nx=600, ny=100)
+    rho, ux, T = f["rho"], f["ux"], f["T"]
+    pr = rho * T
+    # far right: post-shock state; also the fixed inflow state of the x_hi side
+    post = [rho[50, 599], ux[50, 599], 0.0, pr[50, 599]]
+    for got, want, tol in zip(post, g["post"], (5e-3, 5e-5, 0, 5e-5)):
+        assert abs(got - want) <= tol
+    w = p["wall"][1]
+    assert abs(w[0] - rho[50, 599]) < 1e-12 and abs(w[1] - ux[50, 599]) < 1e-12 and abs(w[3] - T[50, 599]) < 1e-12
+    assert p["bc"] == ["zero_gradient", "dirichlet_eq", "specular", "specular"]
+    # far left: gas at rest; bubble centre: the light gas at the same pressure
+    assert abs(rho[50, 0] - g["pre"][0]) < 1e-12 and abs(pr[50, 0] - g["pre"][3]) < 1e-12 and ux[50, 0] == 0.0
+    assert abs(rho[49, 449] - g["bubble"][0]) < 1e-5 and abs(pr[49, 449] - g["bubble"][3]) < 1e-5
+    # the shock sits between nodes 499 and 500 (the paper's 1-based [501, 600])
+    assert rho[10, 497] < 1.05 and rho[10, 502] > 1.23
+    assert m["radius"] == 20.0 and m["center"] == (449.0, 49.5)
