@@ -18,7 +18,10 @@
 //   modification   extra terms in Q_7 and Q_8 (Sec. II, energy-flux modification)
 //   collision      -dt M^-1 Q
 //   convection     forward Euler in time, per-axis central Lax-Wendroff in
-//                  space, read off the amplification matrix G_ij (Sec. III)
+//                  space, read off the amplification matrix G_ij (Sec. III);
+//                  optionally (scheme 1) the same Lax-Wendroff update with a
+//                  minmod limiter on its anti-diffusive flux (flux-limited,
+//                  total-variation-diminishing form; radius 2)
 //   walls          non-equilibrium extrapolation (Sec. IV.A)
 //
 // Readings where the paper is silent (each listed in the design notes):
@@ -29,7 +32,11 @@
 //     walled axis, take rho from the adjacent fluid node and copy that node's
 //     non-equilibrium part, evaluated after the interior update;
 //   * ghost layers: periodic wrap, zero-gradient copy, specular mirror (the
-//     normal velocity component negated), or the equilibrium of a fixed state.
+//     normal velocity component negated), or the equilibrium of a fixed state;
+//     two layers deep for the radius-2 scheme: the second zero-gradient layer
+//     repeats the boundary node, the second mirror layer mirrors the node
+//     next to it (reflection about the wall half a spacing outside the
+//     boundary node).
 //
 // Parity status: the algorithm is pinned by the CPU tests (closed-form
 // equilibria, transport coefficients, thermal Couette profile, gamma = 2
@@ -142,6 +149,7 @@ typedef struct {
   int32_t modified;    // 0 unmodified; 1 modified (Eq. 5 consistent); 2 modified, Q_8 sign as printed
   int32_t bc[4];       // x_lo, x_hi, y_lo, y_hi
   double wall[4][4];   // per side: rho, ux, uy, T
+  int32_t scheme;      // 0 Lax-Wendroff (Sec. III); 1 the same with a minmod flux limiter
 } oracle_params;
 }
 
@@ -275,11 +283,13 @@ inline bool is_wall_node(const oracle_params& p, int x, int y) {
   return false;
 }
 
-// The distribution at the stencil point (x + ox, y + oy), |ox| + |oy| = 1, of
-// node (x, y): a stored node, or a ghost built by that side's condition.
+// The distribution at grid point (xn, yn), which lies inside the domain or in
+// a ghost layer of one side: a stored node, or a ghost built by that side's
+// condition (periodic wrap, zero-gradient copy of the boundary node, mirror
+// image about the wall half a spacing outside the boundary node with the
+// normal velocity negated, or the equilibrium of the side's fixed state).
 template <class R>
-void stencil_point(const oracle_params& p, const Grid<R>& g, int x, int y, int ox, int oy, R* out) {
-  int xn = x + ox, yn = y + oy;
+void point_value(const oracle_params& p, const Grid<R>& g, int xn, int yn, R* out) {
   int side = -1;
   if (xn < 0) side = SIDE_XLO;
   if (xn >= p.nx) side = SIDE_XHI;
@@ -291,22 +301,63 @@ void stencil_point(const oracle_params& p, const Grid<R>& g, int x, int y, int o
     return;
   }
   const int kind = p.bc[side];
-  if (kind == BC_PERIODIC) {
-    xn = (xn + p.nx) % p.nx;
-    yn = (yn + p.ny) % p.ny;
-    const R* src = g.at(xn, yn);
-    for (int i = 0; i < NQ; ++i) out[i] = src[i];
-  } else if (kind == BC_ZERO_GRADIENT) {
-    const R* src = g.at(x, y);
-    for (int i = 0; i < NQ; ++i) out[i] = src[i];
-  } else if (kind == BC_SPECULAR) {
-    const R* src = g.at(x, y);
-    const int* perm = (side == SIDE_XLO || side == SIDE_XHI) ? MIRROR_X : MIRROR_Y;
-    for (int i = 0; i < NQ; ++i) out[i] = src[perm[i]];
-  } else {  // BC_DIRICHLET_EQ (a wall side never needs a ghost: its nodes are not stepped)
+  const bool xside = side == SIDE_XLO || side == SIDE_XHI;
+  const int n = xside ? p.nx : p.ny;
+  int k = xside ? xn : yn;
+  if (kind == BC_DIRICHLET_EQ) {  // (a wall side never needs a ghost: its nodes are not stepped)
     const double* w = p.wall[side];
     feq_distribution<R>(p.eq_version, R(w[0]), R(w[1]), R(w[2]), R(w[3]), out);
+    return;
   }
+  if (kind == BC_PERIODIC) k = ((k % n) + n) % n;
+  else if (kind == BC_ZERO_GRADIENT) k = (k < 0) ? 0 : n - 1;
+  else k = (k < 0) ? -1 - k : 2 * n - 1 - k;  // specular mirror image
+  if (k < 0) k = 0;
+  if (k > n - 1) k = n - 1;
+  const R* src = xside ? g.at(k, yn) : g.at(xn, k);
+  if (kind == BC_SPECULAR) {
+    const int* perm = xside ? MIRROR_X : MIRROR_Y;
+    for (int i = 0; i < NQ; ++i) out[i] = src[perm[i]];
+  } else {
+    for (int i = 0; i < NQ; ++i) out[i] = src[i];
+  }
+}
+
+// The distribution at the stencil point (x + ox, y + oy) of node (x, y).
+template <class R>
+void stencil_point(const oracle_params& p, const Grid<R>& g, int x, int y, int ox, int oy, R* out) {
+  point_value(p, g, x + ox, y + oy, out);
+}
+
+inline double real_part(double v) { return v; }
+inline double real_part(const std::complex<double>& v) { return v.real(); }
+
+// minmod(a, b): the argument of smaller magnitude when both have the same
+// sign, else 0 (decisions on the real part, so that the complex build takes
+// the derivative of the branch the real computation takes).
+template <class R>
+R minmod(R a, R b) {
+  const double ra = real_part(a), rb = real_part(b);
+  if (!(ra * rb > 0.0)) return R(0);
+  return (std::fabs(ra) < std::fabs(rb)) ? a : b;
+}
+
+// Convection increment of one distribution along one axis for the
+// flux-limited scheme: Lax-Wendroff (Sec. III) whose anti-diffusive flux
+// (c/2)(1-|c|)(f_{j+1} - f_j) is limited by minmod of the two adjacent
+// differences; c = v dt / dx, f2m .. f2p the values at j-2 .. j+2. With the
+// limiter replaced by its first argument it is exactly Sec. III's scheme.
+template <class R>
+R limited_lw(double c, R f2m, R f1m, R f0, R f1p, R f2p) {
+  const R dm = f0 - f1m, dp = f1p - f0;
+  if (c > 0.0) {
+    const double k = 0.5 * c * (1.0 - c);
+    const R dmm = f1m - f2m;
+    return -c * dm - k * (minmod(dp, dm) - minmod(dm, dmm));
+  }
+  const double a = -c, k = 0.5 * a * (1.0 - a);
+  const R dpp = f2p - f1p;
+  return a * dp - k * (minmod(dp, dpp) - minmod(dm, dp));
 }
 
 template <class R>
@@ -329,6 +380,14 @@ void update_node(const oracle_params& p, const R* s, const Grid<R>& g, int x, in
   stencil_point(p, g, x, y, -1, 0, fxm);
   stencil_point(p, g, x, y, 0, +1, fyp);
   stencil_point(p, g, x, y, 0, -1, fym);
+  // Second neighbours, used by the flux-limited scheme only.
+  R fxp2[NQ], fxm2[NQ], fyp2[NQ], fym2[NQ];
+  if (p.scheme == 1) {
+    stencil_point(p, g, x, y, +2, 0, fxp2);
+    stencil_point(p, g, x, y, -2, 0, fxm2);
+    stencil_point(p, g, x, y, 0, +2, fyp2);
+    stencil_point(p, g, x, y, 0, -2, fym2);
+  }
 
   // Moments and macroscopic variables at the node.
   R fh[NQ];
@@ -373,11 +432,19 @@ void update_node(const oracle_params& p, const R* s, const Grid<R>& g, int x, in
     }
     coll = -p.dt * coll;
 
-    // Central Lax-Wendroff convection, axis by axis, as in G_ij (Sec. III).
     const double cx = VEL[i][0] * p.dt / p.dx;
     const double cy = VEL[i][1] * p.dt / p.dy;
-    R conv = -0.5 * cx * (fxp[i] - fxm[i]) + 0.5 * cx * cx * (fxp[i] - 2.0 * f[i] + fxm[i]) -
+    R conv;
+    if (p.scheme == 0) {
+      // Central Lax-Wendroff convection, axis by axis, as in G_ij (Sec. III).
+      conv = -0.5 * cx * (fxp[i] - fxm[i]) + 0.5 * cx * cx * (fxp[i] - 2.0 * f[i] + fxm[i]) -
              0.5 * cy * (fyp[i] - fym[i]) + 0.5 * cy * cy * (fyp[i] - 2.0 * f[i] + fym[i]);
+    } else {
+      // The same scheme with a minmod-limited anti-diffusive flux, axis by axis.
+      conv = R(0);
+      if (VEL[i][0] != 0) conv += limited_lw(cx, fxm2[i], fxm[i], f[i], fxp[i], fxp2[i]);
+      if (VEL[i][1] != 0) conv += limited_lw(cy, fym2[i], fym[i], f[i], fyp[i], fyp2[i]);
+    }
     out[i] = f[i] + conv + coll;
   }
 }
@@ -423,6 +490,7 @@ int check_params(const oracle_params* p) {
   if (!(p->dx > 0) || !(p->dy > 0) || !(p->dt > 0)) return -1;
   if (p->eq_version < 1 || p->eq_version > 3) return -1;
   if (p->modified < 0 || p->modified > 2) return -1;
+  if (p->scheme < 0 || p->scheme > 1) return -1;
   for (int a = 0; a < 2; ++a) {
     int lo = p->bc[2 * a], hi = p->bc[2 * a + 1];
     if (lo < 0 || lo > 4 || hi < 0 || hi > 4) return -1;
