@@ -304,6 +304,10 @@ def main():
         pr, flr, _ = inputs.riemann("sod", nx=2000, ny=4)
         log("riemann 2000x4")
         extra["riemann_2000x4"] = run_problem(pr, flr, 2000, 100)
+        pl, fll, _ = inputs.rm(seed=0, nx=nx, ny=ny, width_cells=0.5)
+        pl["scheme"] = 1
+        log("rm %dx%d, flux-limited scheme, sharp interface" % (nx, ny))
+        extra["rm_%dx%d_limited" % (nx, ny)] = run_problem(pl, fll, 100, 10, tune=True)
         log("batch: 512 uneven instances, batched form vs plain path")
         extra["batch_512"] = bench_batch(1000)
         log("adjoint rm 512x128, 2000 steps")

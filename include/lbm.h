@@ -67,7 +67,15 @@ enum { LBM_SIDE_XLO = 0, LBM_SIDE_XHI = 1, LBM_SIDE_YLO = 2, LBM_SIDE_YHI = 3 };
  *               with that term's sign exactly as printed (Sec. II)
  *   bc[4]       lbm_bc per side (x_lo, x_hi, y_lo, y_hi); NEQ walls may be on
  *               one axis only and that axis needs >= 3 nodes
- *   wall[4][4]  per side (rho, ux, uy, T), used by NEQ_WALL and DIRICHLET_EQ */
+ *   wall[4][4]  per side (rho, ux, uy, T), used by NEQ_WALL and DIRICHLET_EQ
+ *   scheme      convection: 0 the central Lax-Wendroff update (Sec. III, the
+ *               paper's scheme, default); 1 the same update with a minmod
+ *               limiter on its anti-diffusive flux (total variation
+ *               diminishing, radius 2, two ghost layers: the second
+ *               zero-gradient layer repeats the boundary node, the second
+ *               mirror layer mirrors the node next to it). Scheme 1 takes
+ *               sharp discontinuities without smoothing; it is not available
+ *               with NEQ walls, in the batched form or in the adjoint form. */
 typedef struct {
   int32_t nx, ny;
   double dx, dy, dt;
@@ -76,6 +84,7 @@ typedef struct {
   int32_t modified;
   int32_t bc[4];
   double wall[4][4];
+  int32_t scheme;
 } lbm_params;
 
 typedef struct lbm_handle lbm_handle;
@@ -91,8 +100,8 @@ size_t lbm_workspace_bytes(const lbm_params* p);
  * nx or ny < 1, dx, dy or dt <= 0, s_k <= 0 for k >= 5, max_k s_k dt > 2
  * (explicit relaxation unstable), unpaired periodic sides, NEQ walls on both
  * axes or on an axis with < 3 nodes, eq_version not in {1,2,3}, modified not
- * in {0,1,2}; LBM_ENOMEM if ws_bytes is too small. The handle owns only host
- * metadata. */
+ * in {0,1,2}, scheme not in {0,1} or scheme 1 with NEQ walls; LBM_ENOMEM if
+ * ws_bytes is too small. The handle owns only host metadata. */
 lbm_status lbm_create(const lbm_params* p, void* d_workspace, size_t ws_bytes, void* hip_stream,
                       lbm_handle** out);
 
@@ -105,8 +114,9 @@ lbm_status lbm_init(lbm_handle* h, const double* d_rho, const double* d_ux, cons
  * Q_k = s_k (f^_k - f^eq_k) plus the energy-flux modification of Q_7, Q_8
  * (Sec. II), collision -dt M^-1 Q, and per-axis central Lax-Wendroff
  * convection with forward-Euler time stepping (the scheme whose amplification
- * matrix is G_ij, Sec. III). Velocity gradients in the modification are
- * central differences of nodal velocities at the old time level. */
+ * matrix is G_ij, Sec. III; with scheme 1 its minmod flux-limited form).
+ * Velocity gradients in the modification are central differences of nodal
+ * velocities at the old time level. */
 lbm_status lbm_step(lbm_handle* h, int64_t nsteps);
 
 /* rho, u_x, u_y, T = e/rho - u^2/2 and p = rho T of the current state

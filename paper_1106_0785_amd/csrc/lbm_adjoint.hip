@@ -28,6 +28,7 @@ lbm_status adj_layout(const lbm_params* p, int64_t nsteps, int32_t ckpt, AdjLayo
   lbm_status st = validate(p);
   if (st != LBM_OK) return st;
   if (has_walls(p)) return fail(LBM_EINVAL, "the adjoint form does not support NEQ walls");
+  if (p->scheme != 0) return fail(LBM_EINVAL, "the adjoint form supports scheme 0 (Lax-Wendroff) only");
   if (nsteps < 1) return fail(LBM_EINVAL, "nsteps must be >= 1");
   if (ckpt < 0) return fail(LBM_EINVAL, "checkpoint interval must be >= 0");
   L->C = ckpt > 0 ? ckpt : std::max(1, (int)std::lround(std::sqrt((double)nsteps)));
@@ -95,7 +96,7 @@ struct lbm_adjoint {
 };
 
 static hipError_t step_into(lbm_adjoint* a, const double* fin, double* fout) {
-  return launch_step(a->field(fin, fout), a->dhot(), a->dcold(), a->p.eq_version, false, 0,
+  return launch_step(a->field(fin, fout), a->dhot(), a->dcold(), a->p.eq_version, false, 0, 0,
                      default_tile(a->p.nx, a->p.ny), a->flag(), a->stream);
 }
 

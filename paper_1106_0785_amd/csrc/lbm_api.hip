@@ -61,6 +61,7 @@ lbm_status validate(const lbm_params* p) {
     return fail(LBM_EINVAL, "max_k s_k dt = %g > 2: the explicit relaxation is unstable", smax * p->dt);
   if (p->eq_version < 1 || p->eq_version > 3) return fail(LBM_EINVAL, "eq_version must be 1, 2 or 3");
   if (p->modified < 0 || p->modified > 2) return fail(LBM_EINVAL, "modified must be 0, 1 or 2");
+  if (p->scheme < 0 || p->scheme > 1) return fail(LBM_EINVAL, "scheme must be 0 or 1");
   for (int k = 0; k < 4; ++k)
     if (p->bc[k] < 0 || p->bc[k] > 4) return fail(LBM_EINVAL, "bc[%d] = %d is not a boundary kind", k, p->bc[k]);
   for (int a = 0; a < 2; ++a)
@@ -69,6 +70,7 @@ lbm_status validate(const lbm_params* p) {
   const bool xw = p->bc[0] == LBM_BC_NEQ_WALL || p->bc[1] == LBM_BC_NEQ_WALL;
   const bool yw = p->bc[2] == LBM_BC_NEQ_WALL || p->bc[3] == LBM_BC_NEQ_WALL;
   if (xw && yw) return fail(LBM_EINVAL, "NEQ walls on both axes are not supported");
+  if ((xw || yw) && p->scheme == 1) return fail(LBM_EINVAL, "NEQ walls are not supported with scheme 1");
   if (xw && p->nx < 3) return fail(LBM_EINVAL, "NEQ walls on x need nx >= 3");
   if (yw && p->ny < 3) return fail(LBM_EINVAL, "NEQ walls on y need ny >= 3");
   if (p->nx == 1 && p->bc[0] != LBM_BC_PERIODIC) return fail(LBM_EINVAL, "an axis of extent 1 must be periodic");
@@ -104,6 +106,10 @@ void make_coef(const lbm_params* p, Hot* c, Cold* cold) {
     c->lx[2 * (v - 1) + 1] = 0.5 * cx * cx + 0.5 * cx;
     c->ly[2 * (v - 1)] = 0.5 * cy * cy - 0.5 * cy;
     c->ly[2 * (v - 1) + 1] = 0.5 * cy * cy + 0.5 * cy;
+    c->tx[2 * (v - 1)] = cx;
+    c->tx[2 * (v - 1) + 1] = 0.5 * cx * (1.0 - cx);
+    c->ty[2 * (v - 1)] = cy;
+    c->ty[2 * (v - 1) + 1] = 0.5 * cy * (1.0 - cy);
   }
   for (int sd = 0; sd < 4; ++sd) {
     for (int j = 0; j < 4; ++j) cold->wall[sd][j] = p->wall[sd][j];
@@ -113,6 +119,7 @@ void make_coef(const lbm_params* p, Hot* c, Cold* cold) {
   }
   c->version = p->eq_version;
   c->modified = p->modified;
+  c->scheme = p->scheme;
 }
 
 MarchGeom march_geom(int nx, int ny, TileShape t) {
@@ -127,8 +134,8 @@ MarchGeom march_geom(int nx, int ny, TileShape t) {
   return g;
 }
 
-hipError_t launch_step(const Field& F, const Hot* c, const Cold* cold, int version, bool walls, int variant,
-                       TileShape t, int* flag, hipStream_t s) {
+hipError_t launch_step(const Field& F, const Hot* c, const Cold* cold, int version, bool walls, int scheme,
+                       int variant, TileShape t, int* flag, hipStream_t s) {
   if (variant == 1) {
     dim3 block(64, 4);
     dim3 grid((F.nx + 63) / 64, (F.ny + 3) / 4);
@@ -136,15 +143,22 @@ hipError_t launch_step(const Field& F, const Hot* c, const Cold* cold, int versi
     hipLaunchKernelGGL(k, grid, block, 0, s, F, c, cold, flag);
     return hipGetLastError();
   }
-  if (walls || t.waves != 2) t.waves = 4;
+  // NEQ walls and the flux-limited scheme use 4-wave tiles
+  if (walls || scheme == 1 || t.waves != 2) t.waves = 4;
   const MarchGeom g = march_geom(F.nx, F.ny, t);
-  decltype(&k_step_fused<1, false, 4>) k;
+  decltype(&k_step_fused<1, false, 4, 1>) k;
   if (walls)
-    k = version == 2 ? k_step_fused<2, true, 4> : version == 3 ? k_step_fused<3, true, 4> : k_step_fused<1, true, 4>;
+    k = version == 2 ? k_step_fused<2, true, 4, 1> : version == 3 ? k_step_fused<3, true, 4, 1>
+                                                                    : k_step_fused<1, true, 4, 1>;
+  else if (scheme == 1)
+    k = version == 2 ? k_step_fused<2, false, 4, 2> : version == 3 ? k_step_fused<3, false, 4, 2>
+                                                                     : k_step_fused<1, false, 4, 2>;
   else if (t.waves == 2)
-    k = version == 2 ? k_step_fused<2, false, 2> : version == 3 ? k_step_fused<3, false, 2> : k_step_fused<1, false, 2>;
+    k = version == 2 ? k_step_fused<2, false, 2, 1> : version == 3 ? k_step_fused<3, false, 2, 1>
+                                                                     : k_step_fused<1, false, 2, 1>;
   else
-    k = version == 2 ? k_step_fused<2, false, 4> : version == 3 ? k_step_fused<3, false, 4> : k_step_fused<1, false, 4>;
+    k = version == 2 ? k_step_fused<2, false, 4, 1> : version == 3 ? k_step_fused<3, false, 4, 1>
+                                                                     : k_step_fused<1, false, 4, 1>;
   hipLaunchKernelGGL(k, dim3(8 * g.per_xcd), dim3(64 * t.waves), 0, s, F, c, cold, g, flag);
   return hipGetLastError();
 }
@@ -256,8 +270,8 @@ lbm_status lbm_step(lbm_handle* h, int64_t nsteps) {
   if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
   for (int64_t n = 0; n < nsteps; ++n) {
     hipError_t e =
-        launch_step(field_of(h, h->cur), &h->dev->hot, &h->dev->cold, h->p.eq_version, has_walls(&h->p), h->variant,
-                    h->tile, h->flag, h->stream);
+        launch_step(field_of(h, h->cur), &h->dev->hot, &h->dev->cold, h->p.eq_version, has_walls(&h->p),
+                    h->p.scheme, h->variant, h->tile, h->flag, h->stream);
     if (e != hipSuccess) return hip_fail(e, "step kernel launch");
     h->cur ^= 1;
   }

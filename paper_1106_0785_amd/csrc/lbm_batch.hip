@@ -77,6 +77,8 @@ static lbm_status layout_of(const lbm_params* inst, int32_t n, Layout* L) {
   for (int i = 0; i < n; ++i) {
     lbm_status st = validate(&inst[i]);
     if (st != LBM_OK) return fail(st, "instance %d: %s", i, lbm_last_error());
+    if (inst[i].scheme != 0)
+      return fail(LBM_EINVAL, "instance %d: the batched form supports scheme 0 (Lax-Wendroff) only", i);
     const lbm_params& p = inst[i];
     if (p.nx != 1 && p.ny != 1)
       return fail(LBM_EINVAL, "instance %d is %d x %d: the batched form takes one-dimensional problems (nx == 1 or ny == 1)",

@@ -30,8 +30,8 @@ struct TileShape {
 };
 MarchGeom march_geom(int nx, int ny, TileShape t);
 bool has_walls(const lbm_params* p);
-hipError_t launch_step(const Field& F, const Hot* c, const Cold* cold, int version, bool walls, int variant,
-                       TileShape t, int* flag, hipStream_t s);
+hipError_t launch_step(const Field& F, const Hot* c, const Cold* cold, int version, bool walls, int scheme,
+                       int variant, TileShape t, int* flag, hipStream_t s);
 TileShape default_tile(int nx, int ny);
 
 }  // namespace lbm

@@ -26,21 +26,25 @@ struct Src {
   int side;
 };
 
+// Ghost layers are up to two deep (radius-2 scheme): a periodic ghost wraps,
+// a zero-gradient ghost repeats the boundary node, a mirror ghost takes the
+// mirror image about the wall half a spacing outside the boundary node
+// (-1 -> 0, -2 -> 1), a fixed-state ghost is that state's equilibrium.
 LBM_HD Src resolve(int i, int n, int bc_lo, int bc_hi, int side_lo) {
   Src s{i, 0, -1};
   if (i < 0) {
     s.side = side_lo;
     switch (bc_lo) {
-      case BC_PERIODIC: s.idx = i + n; break;
-      case BC_SPECULAR: s.idx = 0; s.mode = 1; break;
+      case BC_PERIODIC: s.idx = ((i % n) + n) % n; break;
+      case BC_SPECULAR: s.idx = min(-1 - i, n - 1); s.mode = 1; break;
       case BC_DIRICHLET_EQ: s.idx = 0; s.mode = 2; break;
       default: s.idx = 0; break;  // zero-gradient; a NEQ-wall side's ghost is never used
     }
   } else if (i >= n) {
     s.side = side_lo + 1;
     switch (bc_hi) {
-      case BC_PERIODIC: s.idx = i - n; break;
-      case BC_SPECULAR: s.idx = n - 1; s.mode = 1; break;
+      case BC_PERIODIC: s.idx = i % n; break;
+      case BC_SPECULAR: s.idx = max(2 * n - 1 - i, 0); s.mode = 1; break;
       case BC_DIRICHLET_EQ: s.idx = n - 1; s.mode = 2; break;
       default: s.idx = n - 1; break;
     }
@@ -177,7 +181,20 @@ __global__ __launch_bounds__(256) void k_step_plain(Field F, const Hot* __restri
   velocity_of(fyp, nv.ux_yp, nv.uy_yp);
   velocity_of(fym, nv.ux_ym, nv.uy_ym);
   double out[16];
-  const bool ok = node_update<VER>(c, f, fxp, fxm, fyp, fym, nv, out);
+  bool ok;
+  if (c.scheme == 1) {  // flux-limited: second neighbours too
+    double fxp2[16], fxm2[16], fyp2[16], fym2[16];
+    load_point(F, cold, resolve(x + 2, F.nx, c.bc[0], c.bc[1], 0), cy, fxp2);
+    load_point(F, cold, resolve(x - 2, F.nx, c.bc[0], c.bc[1], 0), cy, fxm2);
+    load_point(F, cold, cx, resolve(y + 2, F.ny, c.bc[2], c.bc[3], 2), fyp2);
+    load_point(F, cold, cx, resolve(y - 2, F.ny, c.bc[2], c.bc[3], 2), fym2);
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+      out[i] = convect_limited_i(c, i, f[i], fxm2[i], fxm[i], fxp[i], fxp2[i], fym2[i], fym[i], fyp[i], fyp2[i]);
+    ok = collide_add<VER>(c, f, nv, out);
+  } else {
+    ok = node_update<VER>(c, f, fxp, fxm, fyp, fym, nv, out);
+  }
   if (!ok) flag[0] = 1;
   store_node(F, x, y, out);
   walls_from<VER>(F, c, cold, x, y, out);
@@ -186,38 +203,59 @@ __global__ __launch_bounds__(256) void k_step_plain(Field F, const Hot* __restri
 // ---------------------------------------------------------------------------
 // Fused kernel. A workgroup of W wavefronts (2 or 4) owns a tile of STRIP =
 // 64 columns (one per lane, 512-byte aligned rows) by `rows` rows and marches
-// up it W rows at a time. Rows y-1 .. y+W live in a ring of W + 2 rows in
-// LDS, each RW = 66 entries wide: the left neighbour column x0-1, the 64
-// strip columns, the right neighbour column x0+64, with 16 distributions and
-// the velocity per entry. Each distribution is read from HBM about once and
-// every lane stores a node (columns past nx land in the row padding), so the
-// stores are full, aligned lines. Each wave keeps its next row in flight in
-// registers while it computes the current one; the two neighbour columns of
-// a row come with one extra load (lane l holds plane l & 15 of the left
-// (l & 16 == 0) or right neighbour) and their velocities from a sum over the
-// 16 lanes of a DPP row.
+// up it W rows at a time. With a stencil of radius HR (1: Lax-Wendroff; 2:
+// its flux-limited form), rows y-HR .. y+W-1+HR live in a ring of W + 2 HR
+// rows in LDS, each STRIP + 2 HR entries wide: the HR neighbour columns left
+// of the strip, the 64 strip columns, the HR neighbour columns right of it,
+// with 16 distributions and the velocity per entry. Each distribution is read
+// from HBM about once and every lane stores a node (columns past nx land in
+// the row padding), so the stores are full, aligned lines. Each wave keeps
+// its next row in flight in registers while it computes the current one; the
+// neighbour columns of a row come with one extra load (lane l holds plane
+// l & 15 of neighbour column (l >> 4) mod 2 HR) and their velocities from a
+// sum over the 16 lanes of a DPP row.
 // ---------------------------------------------------------------------------
 constexpr int STRIP = 64;
 constexpr int WAVES = 4;  // wavefronts per workgroup of the default tile shape
 constexpr int NV = 18;    // 16 distributions + u_x + u_y per ring entry
-constexpr int RW = STRIP + 2;
 
 // Convection of all 16 velocities with the stencil values read from the LDS
 // ring rows (current row r0, rows above/below rp/rm) as they are needed; c0,
 // cp, cm are the ring columns of the node and its x+1 / x-1 neighbours.
-template <int I>
+template <int I, int RWT>
 struct ConvLds {
-  __device__ __forceinline__ static void run(const Hot& c, const double (*r0)[RW], const double (*rp)[RW],
-                                             const double (*rm)[RW], int c0, int cp, int cm, double* out) {
+  __device__ __forceinline__ static void run(const Hot& c, const double (*r0)[RWT], const double (*rp)[RWT],
+                                             const double (*rm)[RWT], int c0, int cp, int cm, double* out) {
     out[I] = convect<I>(c, r0[I][c0], VX[I] ? r0[I][cp] : 0.0, VX[I] ? r0[I][cm] : 0.0,
                         VY[I] ? rp[I][c0] : 0.0, VY[I] ? rm[I][c0] : 0.0);
-    ConvLds<I + 1>::run(c, r0, rp, rm, c0, cp, cm, out);
+    ConvLds<I + 1, RWT>::run(c, r0, rp, rm, c0, cp, cm, out);
   }
 };
-template <>
-struct ConvLds<16> {
-  __device__ __forceinline__ static void run(const Hot&, const double (*)[RW], const double (*)[RW],
-                                             const double (*)[RW], int, int, int, double*) {}
+template <int RWT>
+struct ConvLds<16, RWT> {
+  __device__ __forceinline__ static void run(const Hot&, const double (*)[RWT], const double (*)[RWT],
+                                             const double (*)[RWT], int, int, int, double*) {}
+};
+
+// The same for the flux-limited scheme: rows y-2 .. y+2 (r2m .. r2p) and
+// columns c0-2 .. c0+2.
+template <int I, int RWT>
+struct ConvLim {
+  __device__ __forceinline__ static void run(const Hot& c, const double (*r2m)[RWT], const double (*r1m)[RWT],
+                                             const double (*r0)[RWT], const double (*r1p)[RWT],
+                                             const double (*r2p)[RWT], int c0, double* out) {
+    out[I] = convect_limited<I>(c, r0[I][c0], VX[I] ? r0[I][c0 - 2] : 0.0, VX[I] ? r0[I][c0 - 1] : 0.0,
+                                VX[I] ? r0[I][c0 + 1] : 0.0, VX[I] ? r0[I][c0 + 2] : 0.0,
+                                VY[I] ? r2m[I][c0] : 0.0, VY[I] ? r1m[I][c0] : 0.0, VY[I] ? r1p[I][c0] : 0.0,
+                                VY[I] ? r2p[I][c0] : 0.0);
+    ConvLim<I + 1, RWT>::run(c, r2m, r1m, r0, r1p, r2p, c0, out);
+  }
+};
+template <int RWT>
+struct ConvLim<16, RWT> {
+  __device__ __forceinline__ static void run(const Hot&, const double (*)[RWT], const double (*)[RWT],
+                                             const double (*)[RWT], const double (*)[RWT], const double (*)[RWT], int,
+                                             double*) {}
 };
 
 // Lane value from another lane of the same row of 16 (DPP control CTRL).
@@ -259,13 +297,17 @@ struct MarchGeom {
 // same L2.
 __device__ __forceinline__ int xcd_tile(int b, const MarchGeom& g) { return (b % 8) * g.per_xcd + b / 8; }
 
-// W wavefronts per workgroup (2 or 4); the ring holds RING = W + 2 rows.
-template <int VER, bool WALLS, int W>
+// W wavefronts per workgroup (2 or 4); HR stencil radius (1: Lax-Wendroff,
+// 2: flux-limited); the ring holds RING = W + 2 HR rows.
+template <int VER, bool WALLS, int W, int HR>
 __global__ __launch_bounds__(64 * W, 2) void k_step_fused(Field F, const Hot* __restrict__ hot,
                                                            const Cold* __restrict__ cold, MarchGeom g, int* flag) {
   constexpr int WAVES = W;
-  constexpr int RING = W + 2;
-  __shared__ double ring[RING][NV][RW];
+  constexpr int RING = W + 2 * HR;
+  constexpr int RWT = STRIP + 2 * HR;
+  static_assert(HR == 1 || HR == 2, "stencil radius 1 or 2");
+  static_assert(!WALLS || HR == 1, "NEQ walls with the radius-1 scheme only");
+  __shared__ double ring[RING][NV][RWT];
   __shared__ Hot hs;
   const int tile = xcd_tile(blockIdx.x, g);
   if (tile >= g.ntiles) return;  // whole workgroup leaves together
@@ -280,41 +322,43 @@ __global__ __launch_bounds__(64 * W, 2) void k_step_fused(Field F, const Hot* __
   const int x = x0 + lane;
   const int y0 = seg * g.rows;
   const int y1 = min(y0 + g.rows, F.ny);
-  // this lane's column: x = nx is the right ghost; lanes past it read column
-  // nx-1 and store into the row padding
-  const Src sx = (x <= F.nx) ? resolve(x, F.nx, c.bc[0], c.bc[1], 0) : Src{F.nx - 1, 0, -1};
-  const int c0 = lane + 1;  // ring column of this lane's node
-  const int base = y0 - 1;  // row held in ring slot 0 at the start
+  const int ylast = y1 - 1 + HR;  // last ring row the tile reads
+  // this lane's column: x = nx .. nx+HR-1 are right ghosts; lanes past them
+  // read column nx-1 and store into the row padding
+  const Src sx = (x < F.nx + HR) ? resolve(x, F.nx, c.bc[0], c.bc[1], 0) : Src{F.nx - 1, 0, -1};
+  const int c0 = lane + HR;  // ring column of this lane's node
+  const int base = y0 - HR;  // row held in ring slot 0 at the start
   // ghost rows below and above the domain (scalar reads of the BC codes)
   const int bylo = __builtin_amdgcn_readfirstlane(hot->bc[2]);
   const int byhi = __builtin_amdgcn_readfirstlane(hot->bc[3]);
-  const Src ylo = resolve(-1, F.ny, bylo, byhi, 2);
-  const Src yhi = resolve(F.ny, F.ny, bylo, byhi, 2);
-  auto ysrc = [&](int yr) -> Src { return yr < 0 ? ylo : (yr >= F.ny ? yhi : Src{yr, 0, -1}); };
+  auto ysrc = [&](int yr) -> Src {
+    return (yr >= 0 && yr < F.ny) ? Src{yr, 0, -1} : resolve(yr, F.ny, bylo, byhi, 2);
+  };
 
-  // neighbour-column value of this lane: plane ep of column x0-1 (es = 0) or
-  // x0+64 (es = 1), with the x ghost rule folded into the address (mirror:
-  // mirrored plane; fixed state: the ghost value, same for every row). Only
-  // rows inside the domain use these columns, so no y ghost rule is needed.
-  const int ep = lane & 15, es = (lane >> 4) & 1;
-  const int ecol = es ? RW - 1 : 0;
+  // neighbour-column value of this lane: plane ep of neighbour column e
+  // (ring column ecol, grid column x0 - HR + ecol), with the x ghost rule
+  // folded into the address (mirror: mirrored plane; fixed state: the ghost
+  // value, same for every row). Only rows inside the domain use these
+  // columns, so no y ghost rule is needed.
+  const int ep = lane & 15, e = (lane >> 4) & (2 * HR - 1);
+  const int ecol = (e < HR) ? e : STRIP + e;
   const double* eptr;
   long long estride;
   {
-    const int ex = es ? x0 + STRIP : x0 - 1;
-    const Src e = (ex <= F.nx) ? resolve(ex, F.nx, c.bc[0], c.bc[1], 0) : Src{F.nx - 1, 0, -1};
-    if (e.mode == 2) {
-      eptr = &cold->ghost[e.side][ep];
+    const int ex = x0 - HR + ecol;
+    const Src es = (ex < F.nx + HR) ? resolve(ex, F.nx, c.bc[0], c.bc[1], 0) : Src{F.nx - 1, 0, -1};
+    if (es.mode == 2) {
+      eptr = &cold->ghost[es.side][ep];
       estride = 0;
     } else {
-      const int pl = (e.mode == 1) ? lane_table(MIRROR_X, ep) : ep;
-      eptr = F.fin + (long long)pl * F.plane + e.idx;
+      const int pl = (es.mode == 1) ? lane_table(MIRROR_X, ep) : ep;
+      eptr = F.fin + (long long)pl * F.plane + es.idx;
       estride = F.pitch;
     }
   }
   const double evx = (double)lane_table(VX, ep), evy = (double)lane_table(VY, ep);
 
-  auto to_ring = [&](int slot, const double* f, double e) {
+  auto to_ring = [&](int slot, const double* f, double ev) {
     double ux, uy;
     velocity_of(f, ux, uy);
 #pragma unroll
@@ -322,19 +366,19 @@ __global__ __launch_bounds__(64 * W, 2) void k_step_fused(Field F, const Hot* __
     ring[slot][16][c0] = ux;
     ring[slot][17][c0] = uy;
     // neighbour columns: every lane of a DPP row writes the same values
-    ring[slot][ep][ecol] = e;
-    const double er = row16_sum(e), ejx = row16_sum(evx * e), ejy = row16_sum(evy * e);
+    ring[slot][ep][ecol] = ev;
+    const double er = row16_sum(ev), ejx = row16_sum(evx * ev), ejy = row16_sum(evy * ev);
     const double ir = 1.0 / er;
     ring[slot][16][ecol] = ejx * ir;
     ring[slot][17][ecol] = ejy * ir;
   };
 
-  // Prologue: ring rows y0-1 .. y0+W (only those <= y1 are ever read);
-  // wave w fills slots w and w + W (< RING). Every load of the prologue
-  // and of the first prefetch row is issued before any of them is used.
+  // Prologue: ring rows y0-HR .. y0+W-1+HR (only those <= ylast are ever
+  // read); wave w fills slots w and w + W (< RING). Every load of the
+  // prologue and of the first prefetch row is issued before any is used.
   static_assert(RING - WAVES <= WAVES, "each wave fills at most two prologue slots");
   const bool two = w < RING - WAVES;
-  const int ya = min(base + w, y1), yb = min(base + w + WAVES, y1);
+  const int ya = min(base + w, ylast), yb = min(base + w + WAVES, ylast);
   double pa[16], pb[16], pea, peb = 0.0;
   {
     const int ia = ysrc(ya).idx;
@@ -356,16 +400,16 @@ __global__ __launch_bounds__(64 * W, 2) void k_step_fused(Field F, const Hot* __
   // and loads, so the waits before the ring entry cover only `cur`.
   double fa[16], fb[16], ea, eb;
   {
-    const int yn = min(y0 + WAVES + 1 + w, y1);
+    const int yn = min(y0 + WAVES + HR + w, ylast);
     const int yi = ysrc(yn).idx;
     load_raw(F, sx.idx, yi, fa);
     ea = eptr[yi * estride];
   }
-  if (base + w <= y1) {
+  if (base + w <= ylast) {
     fix_ghost(cold, sx, ysrc(base + w), pa);
     to_ring(w, pa, pea);
   }
-  if (two && base + w + WAVES <= y1) {
+  if (two && base + w + WAVES <= ylast) {
     fix_ghost(cold, sx, ysrc(base + w + WAVES), pb);
     to_ring(w + WAVES, pb, peb);
   }
@@ -373,7 +417,7 @@ __global__ __launch_bounds__(64 * W, 2) void k_step_fused(Field F, const Hot* __
   auto iteration = [&](auto full, int Y, double* cur, double& ecur, double* nxt, double& enxt) {
     constexpr bool FULL = decltype(full)::value;
     {
-      const int yi = ysrc(min(Y + 2 * WAVES + 1 + w, y1)).idx;
+      const int yi = ysrc(min(Y + 2 * WAVES + HR + w, ylast)).idx;
       load_raw(F, sx.idx, yi, nxt);
       enxt = eptr[yi * estride];
     }
@@ -384,7 +428,12 @@ __global__ __launch_bounds__(64 * W, 2) void k_step_fused(Field F, const Hot* __
         const int s0 = (y - base) % RING, sp = (y + 1 - base) % RING, sm = (y - 1 - base) % RING;
         double out[16];
         // convection first, reading each neighbour value from LDS as it is used
-        ConvLds<0>::run(c, ring[s0], ring[sp], ring[sm], c0, c0 + 1, c0 - 1, out);
+        if constexpr (HR == 1) {
+          ConvLds<0, RWT>::run(c, ring[s0], ring[sp], ring[sm], c0, c0 + 1, c0 - 1, out);
+        } else {
+          const int sp2 = (y + 2 - base) % RING, sm2 = (y - 2 - base) % RING;
+          ConvLim<0, RWT>::run(c, ring[sm2], ring[sm], ring[s0], ring[sp], ring[sp2], c0, out);
+        }
         double f[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i) f[i] = ring[s0][i][c0];
@@ -403,8 +452,8 @@ __global__ __launch_bounds__(64 * W, 2) void k_step_fused(Field F, const Hot* __
       }
     }
     __syncthreads();
-    const int yn = Y + WAVES + 1 + w;
-    if (FULL || yn <= y1) {
+    const int yn = Y + WAVES + HR + w;
+    if (FULL || yn <= ylast) {
       fix_ghost(cold, sx, ysrc(yn), cur);
       to_ring((yn - base) % RING, cur, ecur);
     }

@@ -20,9 +20,13 @@ struct Hot {
   // c = v dt/dx: coefficient of f(x+1) is p = (c^2 - c)/2 and of f(x-1) is
   // m = (c^2 + c)/2; for v = -1 / -2 the two swap. Stored as p1, m1, p2, m2.
   double lx[4], ly[4];
+  // Flux-limited scheme (scheme 1) along one axis: for speeds 1 and 2,
+  // a = |v| dt/dx and k = a (1 - a)/2. Stored as a1, k1, a2, k2.
+  double tx[4], ty[4];
   int bc[4];
   int version;
   int modified;
+  int scheme;  // 0 Lax-Wendroff (Sec. III); 1 its minmod flux-limited form
 };
 
 // Rarely read per-problem data.
@@ -62,6 +66,48 @@ LBM_HD double convect(const Hot& c, double f, double fxp, double fxm, double fyp
   if (VY[I] == -1) v += c.ly[1] * (fyp - f) + c.ly[0] * (fym - f);
   if (VY[I] == 2) v += c.ly[2] * (fyp - f) + c.ly[3] * (fym - f);
   if (VY[I] == -2) v += c.ly[3] * (fyp - f) + c.ly[2] * (fym - f);
+  return v;
+}
+
+// minmod(a, b): the argument of smaller magnitude when both have the same
+// sign, else 0.
+LBM_HD double minmod(double a, double b) { return (a * b > 0.0) ? (fabs(a) < fabs(b) ? a : b) : 0.0; }
+
+// Flux-limited convection increment along one axis (scheme 1): the
+// Lax-Wendroff update of Sec. III whose anti-diffusive flux k (f(+1) - f) is
+// limited by minmod of the two differences around it; POS: velocity
+// component > 0; (a, k) from Hot::tx / Hot::ty for this speed; f2m .. f2p the
+// values at -2 .. +2 along the axis. With minmod(d1, d2) replaced by d1 it is
+// exactly convect() below.
+template <bool POS>
+LBM_HD double limited_axis(double a, double k, double f2m, double f1m, double f0, double f1p, double f2p) {
+  const double dm = f0 - f1m, dp = f1p - f0;
+  if (POS) return -a * dm - k * (minmod(dp, dm) - minmod(dm, f1m - f2m));
+  return a * dp - k * (minmod(dp, f2p - f1p) - minmod(dm, dp));
+}
+
+// Both axes of velocity I with the flux-limited scheme.
+template <int I>
+LBM_HD double convect_limited(const Hot& c, double f, double x2m, double x1m, double x1p, double x2p, double y2m,
+                              double y1m, double y1p, double y2p) {
+  double v = 0.0;
+  constexpr int ax = VX[I] < 0 ? -VX[I] : VX[I], ay = VY[I] < 0 ? -VY[I] : VY[I];
+  if (ax) v += limited_axis<(VX[I] > 0)>(c.tx[2 * (ax - 1)], c.tx[2 * (ax - 1) + 1], x2m, x1m, f, x1p, x2p);
+  if (ay) v += limited_axis<(VY[I] > 0)>(c.ty[2 * (ay - 1)], c.ty[2 * (ay - 1) + 1], y2m, y1m, f, y1p, y2p);
+  return v;
+}
+
+// convect_limited<I> for a run-time velocity index (unrolled loops only).
+LBM_HD double convect_limited_i(const Hot& c, int i, double f, double x2m, double x1m, double x1p, double x2p,
+                                double y2m, double y1m, double y1p, double y2p) {
+  double v = 0.0;
+#define LBM_CASE(I) \
+  case I: v = convect_limited<I>(c, f, x2m, x1m, x1p, x2p, y2m, y1m, y1p, y2p); break;
+  switch (i) {
+    LBM_CASE(0) LBM_CASE(1) LBM_CASE(2) LBM_CASE(3) LBM_CASE(4) LBM_CASE(5) LBM_CASE(6) LBM_CASE(7)
+    LBM_CASE(8) LBM_CASE(9) LBM_CASE(10) LBM_CASE(11) LBM_CASE(12) LBM_CASE(13) LBM_CASE(14) LBM_CASE(15)
+  }
+#undef LBM_CASE
   return v;
 }
 

@@ -36,6 +36,7 @@ class LbmParams(ctypes.Structure):
         ("modified", ctypes.c_int32),
         ("bc", ctypes.c_int32 * 4),
         ("wall", (ctypes.c_double * 4) * 4),
+        ("scheme", ctypes.c_int32),
     ]
 
     @classmethod
@@ -53,6 +54,7 @@ class LbmParams(ctypes.Structure):
         for a in range(4):
             for b in range(4):
                 p.wall[a][b] = float(wall[a][b])
+        p.scheme = int(d.get("scheme", 0))
         return p
 
 

@@ -52,6 +52,8 @@ def test_valid_problem_sizes_workspace():
         ({"bc": ["periodic", "specular", "periodic", "periodic"]}, "paired"),
         ({"bc": ["neq_wall", "neq_wall", "neq_wall", "neq_wall"]}, "both axes"),
         ({"nx": 1, "bc": ["specular", "specular", "neq_wall", "neq_wall"]}, "extent 1"),
+        ({"scheme": 2}, "scheme"),
+        ({"scheme": 1}, "scheme 1"),  # the Couette problem has NEQ walls
     ],
 )
 def test_invalid_problems_are_rejected(change, needle):
@@ -67,3 +69,18 @@ def test_rate_must_be_positive():
     s[9] = 0.0
     assert _bytes(dict(p, s=s)) == 0
     assert "s_10" in lbm.load().lbm_last_error().decode()
+
+
+def test_batched_and_adjoint_forms_reject_the_limited_scheme():
+    import ctypes
+
+    from paper_1106_0785_amd import autograd, batch
+
+    p, _ = inputs.smooth_periodic(seed=1, nx=40, ny=1)
+    p["scheme"] = 1
+    assert lbm.lbm_workspace_bytes(p) > 0  # valid for the plain path
+    assert batch.lbm_batch_workspace_bytes([p]) == 0
+    assert "scheme 0" in lbm.load().lbm_last_error().decode()
+    q = lbm.LbmParams.from_dict(p)
+    assert autograd._lib().lbm_adjoint_workspace_bytes(ctypes.byref(q), 10, 0) == 0
+    assert "scheme 0" in lbm.load().lbm_last_error().decode()
