@@ -78,8 +78,9 @@ def run_problem(p, fields, steps, warmup, rows=None, tune=False):
     return out
 
 
-def bench_batch(steps, seed=0, n=512, plain=True):
-    """The 512-instance uneven batch: K steps of the batched form (autotuned
+def bench_batch(steps, seed=0, n=512, plain=True, two_d=False):
+    """The 512-instance uneven batch of lines (two_d: the 96-instance batch
+    of 2-D shock/interface problems): K steps of the batched form (autotuned
     schedule, graph replays) against the same K steps of the plain path
     called once per instance (lbm_step on each instance in turn; skipped
     with plain=False)."""
@@ -88,7 +89,7 @@ def bench_batch(steps, seed=0, n=512, plain=True):
     from paper_1106_0785_amd import inputs, lbm
     from paper_1106_0785_amd.batch import Batch
 
-    items = inputs.batch(seed=seed, n=n)
+    items = inputs.rm_batch(seed=seed, n=n) if two_d else inputs.batch(seed=seed, n=n)
     b = Batch([p for _, p, _ in items])
     b.init([f for _, _, f in items])
     sched = b.tune(probe_steps=32, use_cache=False)
@@ -267,8 +268,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--quick", action="store_true", help="headline workload only")
-    ap.add_argument("--only", choices=["batch", "adjoint"], help="run one side measurement alone and print its JSON "
-                    "(for profiling; not the benchmark line)")
+    ap.add_argument("--only", choices=["batch", "batch2d", "adjoint", "limited"], help="run one side measurement alone and print "
+                    "its JSON (for profiling; not the benchmark line)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X (no multi-GPU path); "
@@ -284,8 +285,16 @@ def main():
     if args.only == "batch":
         print(json.dumps(bench_batch(1000, plain=False)), flush=True)
         return
+    if args.only == "batch2d":
+        print(json.dumps(bench_batch(200, n=96, plain=False, two_d=True)), flush=True)
+        return
     if args.only == "adjoint":
         print(json.dumps(bench_adjoint()), flush=True)
+        return
+    if args.only == "limited":
+        pl, fll, _ = inputs.rm(seed=0, nx=4096, ny=1024, width_cells=0.5)
+        pl["scheme"] = 1
+        print(json.dumps(run_problem(pl, fll, args.steps, args.warmup, tune=True)), flush=True)
         return
 
     # headline: HBM-resident RM-shaped problem
@@ -310,6 +319,8 @@ def main():
         extra["rm_%dx%d_limited" % (nx, ny)] = run_problem(pl, fll, 100, 10, tune=True)
         log("batch: 512 uneven instances, batched form vs plain path")
         extra["batch_512"] = bench_batch(1000)
+        log("batch: 96 uneven 2-D shock/interface instances, batched form vs plain path")
+        extra["batch_rm2d_96"] = bench_batch(200, n=96, two_d=True)
         log("adjoint rm 512x128, 2000 steps")
         extra["adjoint_rm_512x128"] = bench_adjoint()
 

@@ -1,19 +1,24 @@
 /*
- * liblbm batched form: many independent one-dimensional problems of uneven
- * length and parameters advanced together (Riemann lines along x with
- * ny = 1, thermal Couette columns along y with nx = 1; Sec. IV of the paper
- * for the problems, Sec. II-III for the step). Conventions as in lbm.h.
+ * liblbm batched form: many independent problems of uneven size and
+ * parameters advanced together (Riemann lines along x with ny = 1, thermal
+ * Couette columns along y with nx = 1, and two-dimensional problems such as
+ * the shock/interface and shock-bubble set-ups; Sec. IV of the paper for the
+ * problems, Sec. II-III for the step). Conventions as in lbm.h.
  *
  * Layout: instance i owns nodes [lbm_batch_offset(b, i), lbm_batch_offset(b,
  * i + 1)) of every concatenated field array (its own [ny][nx] order), and
  * 16 * (its node count) entries of a concatenated distribution array
- * ([16][N_i] per instance, instances back to back).
+ * ([16][ny][nx] per instance, instances back to back).
  *
- * Execution: a workgroup owns one chunk of one instance plus a halo of h
- * nodes, advances it h steps in LDS and writes the chunk back; one call of
- * lbm_batch_step(b, K) is ceil(K/h) such launches over every chunk of every
- * instance, captured once in a hipGraph and replayed on later calls with the
- * same K. Results equal those of lbm_step on each instance alone.
+ * Execution: one-dimensional instances ("lines"; a periodic one only up to
+ * 128 nodes) are cut into chunks; a workgroup owns one chunk plus a halo of
+ * h nodes, advances it h steps in LDS and writes the chunk back, so K steps
+ * are ceil(K/h) launches over every chunk. The other instances ("tiled") are
+ * cut into 64-column tiles of a common height and take one launch per step
+ * and per (equilibrium version, wall variant) group, every tile of every
+ * such instance in the same launch. One call of lbm_batch_step(b, K) is
+ * captured once in a hipGraph and replayed on later calls with the same K.
+ * Results equal those of lbm_step on each instance alone.
  */
 #ifndef LBM_BATCH_H_
 #define LBM_BATCH_H_
@@ -27,9 +32,9 @@ extern "C" {
 typedef struct lbm_batch lbm_batch;
 
 /* Device workspace for n instances (two arenas, a backup arena used by the
- * tuner, descriptors, chunk list, budgets, status); 0 if any instance is
- * invalid (lbm_create's rules), is not one-dimensional (nx == 1 or ny == 1),
- * or is a periodic line longer than 128 nodes. */
+ * tuner, descriptors, chunk and tile lists, budgets, status); 0 if n < 1 or
+ * any instance is invalid (lbm_create's rules) or uses scheme 1 (the batched
+ * form runs the Lax-Wendroff scheme only). */
 size_t lbm_batch_workspace_bytes(const lbm_params* inst, int32_t n);
 
 /* Binds a batch to caller-owned workspace and stream (as lbm_create). */
@@ -55,17 +60,18 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps);
 /* rho, u_x, u_y, T, p of every instance, concatenated (any may be NULL). */
 lbm_status lbm_batch_moments(lbm_batch* b, double* d_rho, double* d_ux, double* d_uy, double* d_T, double* d_p);
 
-/* Current distributions, [16][N_i] per instance, concatenated. */
+/* Current distributions, [16][ny][nx] per instance, concatenated. */
 lbm_status lbm_batch_get_f(lbm_batch* b, double* d_f);
 
-/* Schedule: region = nodes per workgroup (128 or 256), steps_per_launch = h
- * (region - 2 h >= 32), use_graph = capture lbm_batch_step in a hipGraph. */
+/* Schedule of the line instances: region = nodes per workgroup (128 or
+ * 256), steps_per_launch = h (region - 2 h >= 32); use_graph = capture
+ * lbm_batch_step in a hipGraph (all instances). nchunks counts line chunks. */
 lbm_status lbm_batch_set_schedule(lbm_batch* b, int32_t region, int32_t steps_per_launch, int32_t use_graph);
 lbm_status lbm_batch_get_schedule(const lbm_batch* b, int32_t* region, int32_t* steps_per_launch, int32_t* nchunks);
 
-/* Autotuner: times every admissible (region, h) for probe_steps steps on the
- * current state (synchronising the stream), restores the state and keeps the
- * fastest schedule; *best_ms receives its time. */
+/* Autotuner: times every admissible (region, h) for probe_steps steps of the
+ * line instances on the current state (synchronising the stream), restores
+ * the state and keeps the fastest schedule; *best_ms receives its time. */
 lbm_status lbm_batch_tune(lbm_batch* b, int64_t probe_steps, double* best_ms);
 
 /* As lbm_check, for the batch. */

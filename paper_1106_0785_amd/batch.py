@@ -71,7 +71,7 @@ def signature(params):
 
 class Batch:
     """Owner of one batch: workspace tensor + handle. `params` is a list of
-    parameter dicts (one-dimensional problems)."""
+    parameter dicts (one- or two-dimensional problems, scheme 0)."""
 
     def __init__(self, params, device="cuda"):
         import torch

@@ -38,8 +38,11 @@ void launch_line(const double* A, double* B, const LineInst* insts, const LineCh
 struct lbm_batch {
   int n;
   std::vector<lbm_params> params;
-  std::vector<LineInst> host_insts;
-  std::vector<long long> node_off;  // offset of instance i in concatenated field arrays
+  std::vector<int> tiled;            // 1: advanced tile by tile (TileInst), 0: as a line (LineInst)
+  std::vector<LineInst> host_insts;  // indexed by instance (entries of tiled instances unused)
+  std::vector<TileInst> host_tinsts;
+  std::vector<int> tindex;           // instance -> index in host_tinsts, or -1
+  std::vector<long long> node_off;   // offset of instance i in concatenated field arrays
   long long total_nodes;
   long long arena_doubles;
   hipStream_t stream;
@@ -48,54 +51,99 @@ struct lbm_batch {
   double* backup;
   LineInst* insts;
   LineChunk* chunks;
+  TileInst* tinsts;
+  int* tile_inst;  // tile -> index in tinsts, grouped by (version, walls)
+  int ntiles;
+  int tbegin[4][2], tend[4][2];
   int max_chunks;
   int* budget;
   int* flag;
-  int cur;
+  int cur;   // current buffer of the line instances
+  int cur2;  // current buffer of the tiled instances
   Schedule sched;
   int use_graph;
   // chunk ranges per equilibrium version (1..3): [begin, end)
   int vbegin[4], vend[4];
-  // cached graph
-  hipGraphExec_t graph[2];
-  int64_t graph_steps[2];
+  // cached graphs, one per (cur, cur2)
+  hipGraphExec_t graph[4];
+  int64_t graph_steps[4];
 };
 
 static long long line_len(const lbm_params& p) { return (long long)p.nx * p.ny; }
 
 static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
+// A problem runs through the line kernel when it is one-dimensional and, if
+// periodic, fits one line region; otherwise tile by tile.
+static bool is_line(const lbm_params& p) {
+  if (p.nx != 1 && p.ny != 1) return false;
+  const int axis = (p.ny == 1 && p.nx > 1) ? 0 : 1;
+  return !(p.bc[2 * axis] == LBM_BC_PERIODIC && line_len(p) > 128);
+}
+
+// Rows per tile of the tiled instances: the tallest of 64, 32, ... 4 that
+// still gives the whole batch ~1024 tiles (taller tiles re-read fewer halo rows).
+static int batch_tile_rows(const lbm_params* inst, int32_t n) {
+  int rows = 64;
+  for (; rows > WAVES; rows /= 2) {
+    long long tiles = 0;
+    for (int i = 0; i < n; ++i)
+      if (!is_line(inst[i])) tiles += march_geom(inst[i].nx, inst[i].ny, TileShape{rows, WAVES}).ntiles;
+    if (tiles >= 1024) break;
+  }
+  return rows;
+}
+
 struct Layout {
-  size_t arena_bytes, insts_off, chunks_off, budget_off, flag_off, backup_off, total;
+  size_t arena_bytes, insts_off, chunks_off, tinsts_off, tiles_off, budget_off, flag_off, backup_off, total;
   long long arena_doubles;
-  int max_chunks;
+  int max_chunks, ntiled, ntiles;
+  int rows;  // rows per tile of the tiled instances
+  std::vector<long long> off;  // arena offset (doubles) of each instance
 };
 
 static lbm_status layout_of(const lbm_params* inst, int32_t n, Layout* L) {
   if (!inst || n < 1) return fail(LBM_EINVAL, "need at least one instance");
   long long dbl = 0, maxc = 0;
+  int ntiled = 0, ntiles = 0;
+  L->off.assign(n, 0);
   for (int i = 0; i < n; ++i) {
     lbm_status st = validate(&inst[i]);
+    if (st != LBM_OK) return fail(st, "instance %d: %s", i, lbm_last_error());
+  }
+  L->rows = batch_tile_rows(inst, n);
+  for (int i = 0; i < n; ++i) {
+    lbm_status st = LBM_OK;
     if (st != LBM_OK) return fail(st, "instance %d: %s", i, lbm_last_error());
     if (inst[i].scheme != 0)
       return fail(LBM_EINVAL, "instance %d: the batched form supports scheme 0 (Lax-Wendroff) only", i);
     const lbm_params& p = inst[i];
-    if (p.nx != 1 && p.ny != 1)
-      return fail(LBM_EINVAL, "instance %d is %d x %d: the batched form takes one-dimensional problems (nx == 1 or ny == 1)",
-                  i, p.nx, p.ny);
-    const long long N = line_len(p);
-    const int axis = (p.ny == 1 && p.nx > 1) ? 0 : 1;
-    if (p.bc[2 * axis] == LBM_BC_PERIODIC && N > 128)
-      return fail(LBM_EINVAL, "instance %d: a periodic line in the batch must have <= 128 nodes", i);
-    dbl += 16 * ((N + 15) / 16 * 16);
-    maxc += (N + MIN_CHUNK - 1) / MIN_CHUNK + 1;
+    if (is_line(p)) {
+      const long long N = line_len(p);
+      dbl = (dbl + 15) / 16 * 16;
+      L->off[i] = dbl;
+      dbl += 16 * ((N + 15) / 16 * 16);
+      maxc += (N + MIN_CHUNK - 1) / MIN_CHUNK + 1;
+    } else {
+      dbl = (dbl + 63) / 64 * 64;  // 512-byte aligned rows
+      L->off[i] = dbl;
+      dbl += 16 * row_pitch(p.nx) * p.ny;
+      const MarchGeom g = march_geom(p.nx, p.ny, TileShape{L->rows, WAVES});
+      ++ntiled;
+      if ((long long)ntiles + g.ntiles > INT_MAX / 2) return fail(LBM_EINVAL, "batch has too many tiles");
+      ntiles += g.ntiles;
+    }
   }
   L->arena_doubles = dbl;
   L->max_chunks = (int)maxc;
+  L->ntiled = ntiled;
+  L->ntiles = ntiles;
   L->arena_bytes = align256((size_t)dbl * sizeof(double));
   L->insts_off = 2 * L->arena_bytes;
   L->chunks_off = L->insts_off + align256((size_t)n * sizeof(LineInst));
-  L->budget_off = L->chunks_off + align256((size_t)maxc * sizeof(LineChunk));
+  L->tinsts_off = L->chunks_off + align256((size_t)std::max<long long>(maxc, 1) * sizeof(LineChunk));
+  L->tiles_off = L->tinsts_off + align256((size_t)std::max(ntiled, 1) * sizeof(TileInst));
+  L->budget_off = L->tiles_off + align256((size_t)std::max(ntiles, 1) * sizeof(int));
   L->flag_off = L->budget_off + align256((size_t)n * sizeof(int));
   L->backup_off = L->flag_off + 256;
   L->total = L->backup_off + L->arena_bytes;
@@ -103,7 +151,7 @@ static lbm_status layout_of(const lbm_params* inst, int32_t n, Layout* L) {
 }
 
 static void drop_graphs(lbm_batch* b) {
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < 4; ++k) {
     if (b->graph[k]) (void)hipGraphExecDestroy(b->graph[k]);
     b->graph[k] = nullptr;
     b->graph_steps[k] = -1;
@@ -116,7 +164,7 @@ static lbm_status build_chunks(lbm_batch* b, const Schedule& s) {
   for (int ver = 1; ver <= 3; ++ver) {
     b->vbegin[ver] = (int)ch.size();
     for (int i = 0; i < b->n; ++i) {
-      if (b->params[i].eq_version != ver) continue;
+      if (b->params[i].eq_version != ver || b->tiled[i]) continue;
       const int N = b->host_insts[i].N;
       if (N <= s.region) {
         ch.push_back(LineChunk{i, 0, N, 0});
@@ -136,9 +184,15 @@ static lbm_status build_chunks(lbm_batch* b, const Schedule& s) {
   return LBM_OK;
 }
 
-static hipError_t enqueue_steps(lbm_batch* b, int64_t nsteps, int start_cur, hipStream_t stream) {
+// Enqueues nsteps steps of every instance: the line instances as
+// ceil(nsteps / h) temporal-blocking launches starting from buffer
+// start_cur, the tiled instances (unless lines_only) as one launch per step
+// and group starting from buffer start_cur2.
+static hipError_t enqueue_steps(lbm_batch* b, int64_t nsteps, int start_cur, int start_cur2, hipStream_t stream,
+                                bool lines_only = false) {
   int cur = start_cur;
-  for (int64_t n0 = 0; n0 < nsteps; n0 += b->sched.h) {
+  const bool lines = b->vend[3] > b->vbegin[1];
+  for (int64_t n0 = 0; lines && n0 < nsteps; n0 += b->sched.h) {
     const int h = (int)std::min<int64_t>(b->sched.h, nsteps - n0);
     for (int ver = 1; ver <= 3; ++ver) {
       const int nc = b->vend[ver] - b->vbegin[ver];
@@ -164,6 +218,25 @@ static hipError_t enqueue_steps(lbm_batch* b, int64_t nsteps, int start_cur, hip
       if (e != hipSuccess) return e;
     }
     cur ^= 1;
+  }
+  int cur2 = start_cur2;
+  for (int64_t n = 0; !lines_only && b->ntiles > 0 && n < nsteps; ++n) {
+    for (int ver = 1; ver <= 3; ++ver)
+      for (int w = 0; w < 2; ++w) {
+        const int nt = b->tend[ver][w] - b->tbegin[ver][w];
+        if (nt == 0) continue;
+        const int per_xcd = (nt + 7) / 8;
+        decltype(&k_batch_tiles<1, false>) k;
+        if (w)
+          k = ver == 2 ? k_batch_tiles<2, true> : ver == 3 ? k_batch_tiles<3, true> : k_batch_tiles<1, true>;
+        else
+          k = ver == 2 ? k_batch_tiles<2, false> : ver == 3 ? k_batch_tiles<3, false> : k_batch_tiles<1, false>;
+        hipLaunchKernelGGL(k, dim3(8 * per_xcd), dim3(64 * WAVES), 0, stream, b->arena[cur2], b->arena[cur2 ^ 1],
+                           b->tinsts, b->tile_inst + b->tbegin[ver][w], nt, per_xcd, b->budget, (int)n, b->flag);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+      }
+    cur2 ^= 1;
   }
   return hipSuccess;
 }
@@ -199,15 +272,21 @@ lbm_status lbm_batch_create(const lbm_params* inst, int32_t n, void* d_workspace
   b->arena[1] = (double*)(base + L.arena_bytes);
   b->insts = (LineInst*)(base + L.insts_off);
   b->chunks = (LineChunk*)(base + L.chunks_off);
+  b->tinsts = (TileInst*)(base + L.tinsts_off);
+  b->tile_inst = (int*)(base + L.tiles_off);
   b->budget = (int*)(base + L.budget_off);
   b->flag = (int*)(base + L.flag_off);
   b->backup = (double*)(base + L.backup_off);
   b->max_chunks = L.max_chunks;
   b->arena_doubles = L.arena_doubles;
+  b->ntiles = L.ntiles;
   b->cur = 0;
+  b->cur2 = 0;
   b->use_graph = 1;
-  b->graph[0] = b->graph[1] = nullptr;
-  b->graph_steps[0] = b->graph_steps[1] = -1;
+  for (int k = 0; k < 4; ++k) {
+    b->graph[k] = nullptr;
+    b->graph_steps[k] = -1;
+  }
   b->capture = nullptr;
   if (hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking) != hipSuccess) {
     delete b;
@@ -215,24 +294,59 @@ lbm_status lbm_batch_create(const lbm_params* inst, int32_t n, void* d_workspace
   }
   b->host_insts.resize(n);
   b->node_off.resize(n);
-  long long off = 0, node = 0;
+  b->tiled.assign(n, 0);
+  b->tindex.assign(n, -1);
+  long long node = 0;
   for (int i = 0; i < n; ++i) {
     const lbm_params& p = inst[i];
     LineInst& I = b->host_insts[i];
     std::memset(&I, 0, sizeof(I));
+    b->node_off[i] = node;
+    node += line_len(p);
+    if (!is_line(p)) {
+      b->tiled[i] = 1;
+      b->tindex[i] = (int)b->host_tinsts.size();
+      TileInst T;
+      std::memset(&T, 0, sizeof(T));
+      T.off = L.off[i];
+      T.pitch = row_pitch(p.nx);
+      T.plane = T.pitch * p.ny;
+      T.nx = p.nx;
+      T.ny = p.ny;
+      T.gidx = i;
+      T.geom = march_geom(p.nx, p.ny, TileShape{L.rows, WAVES});
+      make_coef(&p, &T.hot, &T.cold);
+      b->host_tinsts.push_back(T);
+      continue;
+    }
     I.N = (int)line_len(p);
     I.stride = (I.N + 15) / 16 * 16;
-    I.off = off;
+    I.off = L.off[i];
     I.axis = (p.ny == 1 && p.nx > 1) ? 0 : 1;
     I.walls = has_walls(&p) ? 1 : 0;
     make_coef(&p, &I.hot, &I.cold);
-    off += 16LL * I.stride;
-    b->node_off[i] = node;
-    node += I.N;
   }
   b->total_nodes = node;
+  // tile list grouped by (equilibrium version, wall variant)
+  std::vector<int> tiles;
+  for (int ver = 1; ver <= 3; ++ver)
+    for (int w = 0; w < 2; ++w) {
+      b->tbegin[ver][w] = (int)tiles.size();
+      for (size_t j = 0; j < b->host_tinsts.size(); ++j) {
+        const lbm_params& p = b->params[b->host_tinsts[j].gidx];
+        if (p.eq_version != ver || (int)has_walls(&p) != w) continue;
+        b->host_tinsts[j].first_tile = (int)tiles.size() - b->tbegin[ver][w];
+        for (int t = 0; t < b->host_tinsts[j].geom.ntiles; ++t) tiles.push_back((int)j);
+      }
+      b->tend[ver][w] = (int)tiles.size();
+    }
   std::vector<int> budget(n, INT_MAX);
   hipError_t e = hipMemcpyAsync(b->insts, b->host_insts.data(), n * sizeof(LineInst), hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess && !b->host_tinsts.empty())
+    e = hipMemcpyAsync(b->tinsts, b->host_tinsts.data(), b->host_tinsts.size() * sizeof(TileInst),
+                       hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess && !tiles.empty())
+    e = hipMemcpyAsync(b->tile_inst, tiles.data(), tiles.size() * sizeof(int), hipMemcpyHostToDevice, b->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(b->budget, budget.data(), n * sizeof(int), hipMemcpyHostToDevice, b->stream);
   if (e == hipSuccess) e = hipMemsetAsync(b->flag, 0, 256, b->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
@@ -257,21 +371,41 @@ int64_t lbm_batch_offset(const lbm_batch* b, int32_t i) {
   return i == b->n ? b->total_nodes : b->node_off[i];
 }
 
+// Field view of instance i in arena buffer buf.
+static Field field_of(const lbm_batch* b, int i, int buf) {
+  const lbm_params& p = b->params[i];
+  Field F;
+  F.nx = p.nx;
+  F.ny = p.ny;
+  double* base;
+  if (b->tiled[i]) {
+    const TileInst& T = b->host_tinsts[b->tindex[i]];
+    base = b->arena[buf] + T.off;
+    F.pitch = T.pitch;
+    F.plane = T.plane;
+  } else {
+    const LineInst& I = b->host_insts[i];
+    base = b->arena[buf] + I.off;
+    F.pitch = p.nx;
+    F.plane = I.stride;
+  }
+  F.fin = base;
+  F.fout = base;
+  return F;
+}
+
+// Buffer holding the current state of instance i.
+static int current_buf(const lbm_batch* b, int i) { return b->tiled[i] ? b->cur2 : b->cur; }
+
 lbm_status lbm_batch_init(lbm_batch* b, const double* d_rho, const double* d_ux, const double* d_uy,
                           const double* d_T) {
   if (!b || !d_rho || !d_ux || !d_uy || !d_T) return fail(LBM_EINVAL, "NULL argument");
   for (int i = 0; i < b->n; ++i) {
     const lbm_params& p = b->params[i];
-    const LineInst& I = b->host_insts[i];
     const long long k = b->node_off[i];
     for (int buf = 0; buf < 2; ++buf) {
-      Field F;
+      Field F = field_of(b, i, buf);
       F.fin = nullptr;
-      F.fout = b->arena[buf] + I.off;
-      F.nx = p.nx;
-      F.ny = p.ny;
-      F.pitch = p.nx;
-      F.plane = I.stride;
       dim3 grid((p.nx + 63) / 64, p.ny);
       auto kern = p.eq_version == 2 ? k_init<2> : p.eq_version == 3 ? k_init<3> : k_init<1>;
       hipLaunchKernelGGL(kern, grid, dim3(64), 0, b->stream, F, d_rho + k, d_ux + k, d_uy + k, d_T + k);
@@ -280,6 +414,7 @@ lbm_status lbm_batch_init(lbm_batch* b, const double* d_rho, const double* d_ux,
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "k_init launch");
   b->cur = 0;
+  b->cur2 = 0;
   return LBM_OK;
 }
 
@@ -303,17 +438,17 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps) {
   if (nsteps == 0) return LBM_OK;
   const int L = launches_for(b, nsteps);
   if (!b->use_graph) {
-    hipError_t e = enqueue_steps(b, nsteps, b->cur, b->stream);
+    hipError_t e = enqueue_steps(b, nsteps, b->cur, b->cur2, b->stream);
     if (e != hipSuccess) return hip_fail(e, "batched step launch");
   } else {
-    const int c = b->cur;
+    const int c = b->cur + 2 * b->cur2;
     if (b->graph_steps[c] != nsteps) {
       if (b->graph[c]) (void)hipGraphExecDestroy(b->graph[c]);
       b->graph[c] = nullptr;
       hipGraph_t g = nullptr;
       hipError_t e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal);
       if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-      e = enqueue_steps(b, nsteps, c, b->capture);
+      e = enqueue_steps(b, nsteps, b->cur, b->cur2, b->capture);
       hipError_t e2 = hipStreamEndCapture(b->capture, &g);
       if ((e != hipSuccess || e2 != hipSuccess) && g) (void)hipGraphDestroy(g);
       if (e != hipSuccess) return hip_fail(e, "capturing the batched steps");
@@ -330,6 +465,7 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps) {
     if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
   }
   if (L & 1) b->cur ^= 1;
+  if (nsteps & 1) b->cur2 ^= 1;
   return LBM_OK;
 }
 
@@ -337,15 +473,9 @@ lbm_status lbm_batch_moments(lbm_batch* b, double* d_rho, double* d_ux, double* 
   if (!b) return fail(LBM_EINVAL, "batch is NULL");
   for (int i = 0; i < b->n; ++i) {
     const lbm_params& p = b->params[i];
-    const LineInst& I = b->host_insts[i];
     const long long k = b->node_off[i];
-    Field F;
-    F.fin = b->arena[b->cur] + I.off;
+    Field F = field_of(b, i, current_buf(b, i));
     F.fout = nullptr;
-    F.nx = p.nx;
-    F.ny = p.ny;
-    F.pitch = p.nx;
-    F.plane = I.stride;
     dim3 grid((p.nx + 63) / 64, p.ny);
     hipLaunchKernelGGL(k_moments<0>, grid, dim3(64), 0, b->stream, F, d_rho ? d_rho + k : nullptr,
                        d_ux ? d_ux + k : nullptr, d_uy ? d_uy + k : nullptr, d_T ? d_T + k : nullptr,
@@ -359,10 +489,15 @@ lbm_status lbm_batch_moments(lbm_batch* b, double* d_rho, double* d_ux, double* 
 lbm_status lbm_batch_get_f(lbm_batch* b, double* d_f) {
   if (!b || !d_f) return fail(LBM_EINVAL, "NULL argument");
   for (int i = 0; i < b->n; ++i) {
-    const LineInst& I = b->host_insts[i];
-    hipError_t e = hipMemcpy2DAsync(d_f + 16 * b->node_off[i], I.N * sizeof(double), b->arena[b->cur] + I.off,
-                                    I.stride * sizeof(double), I.N * sizeof(double), 16, hipMemcpyDeviceToDevice,
-                                    b->stream);
+    const lbm_params& p = b->params[i];
+    const Field F = field_of(b, i, current_buf(b, i));
+    // source rows: 16 planes of ny rows (plane = ny * pitch for tiled
+    // instances, one row of nx = N nodes per plane for lines)
+    const size_t rows = b->tiled[i] ? (size_t)16 * p.ny : 16;
+    const size_t width = b->tiled[i] ? (size_t)p.nx : (size_t)line_len(p);
+    const size_t spitch = b->tiled[i] ? (size_t)F.pitch : (size_t)F.plane;
+    hipError_t e = hipMemcpy2DAsync(d_f + 16 * b->node_off[i], width * sizeof(double), F.fin, spitch * sizeof(double),
+                                    width * sizeof(double), rows, hipMemcpyDeviceToDevice, b->stream);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpy2DAsync");
   }
   return LBM_OK;
@@ -391,6 +526,8 @@ lbm_status lbm_batch_tune(lbm_batch* b, int64_t probe_steps, double* best_ms) {
   if (probe_steps < 1) return fail(LBM_EINVAL, "probe_steps must be >= 1");
   // keep the current state: every trial runs from a backup copy
   const size_t bytes = (size_t)b->arena_doubles * sizeof(double);
+  // (the schedule concerns the line instances only; the trials leave the
+  // tiled instances alone)
   hipError_t e = hipMemcpyAsync(b->backup, b->arena[b->cur], bytes, hipMemcpyDeviceToDevice, b->stream);
   if (e != hipSuccess) return hip_fail(e, "backing up the state");
   const int saved_cur = b->cur;
@@ -411,9 +548,9 @@ lbm_status lbm_batch_tune(lbm_batch* b, int64_t probe_steps, double* best_ms) {
       if (!schedule_ok(s)) continue;
       if (build_chunks(b, s) != LBM_OK) continue;
       // warm-up + timed trial, both without graphs
-      e = enqueue_steps(b, std::min<int64_t>(probe_steps, 2 * h), b->cur, b->stream);
+      e = enqueue_steps(b, std::min<int64_t>(probe_steps, 2 * h), b->cur, b->cur2, b->stream, true);
       if (e == hipSuccess) e = hipEventRecord(t0, b->stream);
-      if (e == hipSuccess) e = enqueue_steps(b, probe_steps, b->cur, b->stream);
+      if (e == hipSuccess) e = enqueue_steps(b, probe_steps, b->cur, b->cur2, b->stream, true);
       if (e == hipSuccess) e = hipEventRecord(t1, b->stream);
       if (e == hipSuccess) e = hipEventSynchronize(t1);
       if (e != hipSuccess) break;

@@ -168,3 +168,55 @@ __global__ __launch_bounds__(REGION, 2) void k_batch_line(const double* __restri
 }
 
 }  // namespace lbm
+
+namespace lbm {
+
+// A batch instance advanced tile by tile with the fused step kernel: the
+// two-dimensional instances, and periodic lines too long for one line region.
+// Its planes are pitched like a single problem's ([16][ny][pitch], pitch = nx
+// rounded up to 64 doubles, 512-byte aligned).
+struct TileInst {
+  long long off;     // offset (doubles) of plane 0 in each arena buffer
+  long long pitch, plane;
+  int nx, ny;
+  int gidx;          // index of the instance in the batch (budgets)
+  int first_tile;    // index of its first tile in the batch's tile list
+  MarchGeom geom;
+  Hot hot;
+  Cold cold;
+};
+
+// One time step of every tile of a group of tile instances (same
+// equilibrium version and wall variant); workgroup b takes tile
+// (b mod 8) per_xcd + b / 8 of the group's list, so each XCD gets a
+// contiguous run. An instance whose budget is spent copies its tile through.
+template <int VER, bool WALLS>
+__global__ __launch_bounds__(64 * WAVES, 2) void k_batch_tiles(const double* __restrict__ A, double* __restrict__ B,
+                                                                const TileInst* __restrict__ insts,
+                                                                const int* __restrict__ tile_inst, int ntiles,
+                                                                int per_xcd, const int* __restrict__ budget, int n,
+                                                                int* flag) {
+  const int t = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (t >= ntiles) return;  // whole workgroup leaves together
+  const TileInst& I = insts[tile_inst[t]];
+  Field F;
+  F.fin = A + I.off;
+  F.fout = B + I.off;
+  F.nx = I.nx;
+  F.ny = I.ny;
+  F.pitch = I.pitch;
+  F.plane = I.plane;
+  const int tile = t - I.first_tile;
+  if (budget[I.gidx] <= n) {
+    const int strip = tile % I.geom.nstrips, seg = tile / I.geom.nstrips;
+    const int x = strip * STRIP + (threadIdx.x & 63);
+    const int y1 = min((seg + 1) * I.geom.rows, I.ny);
+    for (int y = seg * I.geom.rows + (threadIdx.x >> 6); y < y1; y += WAVES)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) F.fout[i * F.plane + (long long)y * F.pitch + x] = F.fin[i * F.plane + (long long)y * F.pitch + x];
+    return;
+  }
+  fused_tile<VER, WALLS, WAVES, 1>(F, &I.hot, &I.cold, I.geom, tile, flag);
+}
+
+}  // namespace lbm

@@ -297,11 +297,12 @@ struct MarchGeom {
 // same L2.
 __device__ __forceinline__ int xcd_tile(int b, const MarchGeom& g) { return (b % 8) * g.per_xcd + b / 8; }
 
-// W wavefronts per workgroup (2 or 4); HR stencil radius (1: Lax-Wendroff,
-// 2: flux-limited); the ring holds RING = W + 2 HR rows.
+// One tile (index `tile` < g.ntiles) of one problem, computed by a workgroup
+// of W wavefronts (2 or 4); HR stencil radius (1: Lax-Wendroff, 2:
+// flux-limited); the ring holds RING = W + 2 HR rows.
 template <int VER, bool WALLS, int W, int HR>
-__global__ __launch_bounds__(64 * W, 2) void k_step_fused(Field F, const Hot* __restrict__ hot,
-                                                           const Cold* __restrict__ cold, MarchGeom g, int* flag) {
+__device__ __forceinline__ void fused_tile(Field F, const Hot* __restrict__ hot, const Cold* __restrict__ cold,
+                                           MarchGeom g, int tile, int* flag) {
   constexpr int WAVES = W;
   constexpr int RING = W + 2 * HR;
   constexpr int RWT = STRIP + 2 * HR;
@@ -309,8 +310,6 @@ __global__ __launch_bounds__(64 * W, 2) void k_step_fused(Field F, const Hot* __
   static_assert(!WALLS || HR == 1, "NEQ walls with the radius-1 scheme only");
   __shared__ double ring[RING][NV][RWT];
   __shared__ Hot hs;
-  const int tile = xcd_tile(blockIdx.x, g);
-  if (tile >= g.ntiles) return;  // whole workgroup leaves together
   stage_hot(hot, &hs);
   const Hot& c = hs;
   const int lane = threadIdx.x & 63;
@@ -331,8 +330,14 @@ __global__ __launch_bounds__(64 * W, 2) void k_step_fused(Field F, const Hot* __
   // ghost rows below and above the domain (scalar reads of the BC codes)
   const int bylo = __builtin_amdgcn_readfirstlane(hot->bc[2]);
   const int byhi = __builtin_amdgcn_readfirstlane(hot->bc[3]);
+  // the (at most HR) ghost rows on each side, resolved once
+  const Src ylo1 = resolve(-1, F.ny, bylo, byhi, 2), yhi1 = resolve(F.ny, F.ny, bylo, byhi, 2);
+  const Src ylo2 = HR > 1 ? resolve(-2, F.ny, bylo, byhi, 2) : ylo1;
+  const Src yhi2 = HR > 1 ? resolve(F.ny + 1, F.ny, bylo, byhi, 2) : yhi1;
   auto ysrc = [&](int yr) -> Src {
-    return (yr >= 0 && yr < F.ny) ? Src{yr, 0, -1} : resolve(yr, F.ny, bylo, byhi, 2);
+    if (yr < 0) return (HR > 1 && yr < -1) ? ylo2 : ylo1;
+    if (yr >= F.ny) return (HR > 1 && yr > F.ny) ? yhi2 : yhi1;
+    return Src{yr, 0, -1};
   };
 
   // neighbour-column value of this lane: plane ep of neighbour column e
@@ -471,6 +476,14 @@ __global__ __launch_bounds__(64 * W, 2) void k_step_fused(Field F, const Hot* __
     iteration(Part{}, Y + WAVES, fb, eb, fa, ea);
   }
   if (!ok) flag[0] = 1;
+}
+
+template <int VER, bool WALLS, int W, int HR>
+__global__ __launch_bounds__(64 * W, 2) void k_step_fused(Field F, const Hot* __restrict__ hot,
+                                                           const Cold* __restrict__ cold, MarchGeom g, int* flag) {
+  const int tile = xcd_tile(blockIdx.x, g);
+  if (tile >= g.ntiles) return;  // whole workgroup leaves together
+  fused_tile<VER, WALLS, W, HR>(F, hot, cold, g, tile, flag);
 }
 
 // ---------------------------------------------------------------------------

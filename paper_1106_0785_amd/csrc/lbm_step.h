@@ -92,8 +92,10 @@ LBM_HD double convect_limited(const Hot& c, double f, double x2m, double x1m, do
                               double y1m, double y1p, double y2p) {
   double v = 0.0;
   constexpr int ax = VX[I] < 0 ? -VX[I] : VX[I], ay = VY[I] < 0 ? -VY[I] : VY[I];
-  if (ax) v += limited_axis<(VX[I] > 0)>(c.tx[2 * (ax - 1)], c.tx[2 * (ax - 1) + 1], x2m, x1m, f, x1p, x2p);
-  if (ay) v += limited_axis<(VY[I] > 0)>(c.ty[2 * (ay - 1)], c.ty[2 * (ay - 1) + 1], y2m, y1m, f, y1p, y2p);
+  if constexpr (ax != 0)
+    v += limited_axis<(VX[I] > 0)>(c.tx[2 * (ax - 1)], c.tx[2 * (ax - 1) + 1], x2m, x1m, f, x1p, x2p);
+  if constexpr (ay != 0)
+    v += limited_axis<(VY[I] > 0)>(c.ty[2 * (ay - 1)], c.ty[2 * (ay - 1) + 1], y2m, y1m, f, y1p, y2p);
   return v;
 }
 

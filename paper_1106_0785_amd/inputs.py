@@ -293,6 +293,60 @@ def batch(seed=0, n=512, riemann_n=(256, 4096), couette_h=(32, 256), pr_range=(0
 
 
 # --------------------------------------------------------------------------
+# Uneven batch mixing the 1-D instances above with 2-D ones: shock/interface
+# (Richtmyer-Meshkov) set-ups of random size, shock-bubble set-ups,
+# Couette channels with two-dimensional extent (NEQ walls), periodic smooth
+# states under the three equilibrium versions, and periodic Riemann lines
+# longer than one line region.
+# --------------------------------------------------------------------------
+def mixed_batch(seed=0, n=24, rm_nx=(64, 320), rm_ny=(8, 72), riemann_n=(200, 900), couette_h=(32, 120)):
+    rng = np.random.default_rng(seed)
+    lines = batch(seed=seed + 1000, n=n, riemann_n=riemann_n, couette_h=couette_h)
+    out = []
+    for i in range(n):
+        kind = i % 6
+        if kind == 0:
+            out.append(lines[i])
+        elif kind == 1:
+            nx = int(rng.integers(rm_nx[0], rm_nx[1] + 1))
+            ny = int(rng.integers(rm_ny[0], rm_ny[1] + 1))
+            p, f, _ = rm(seed=int(rng.integers(0, 1 << 30)), nx=nx, ny=ny)
+            out.append(("rm", p, f))
+        elif kind == 2:
+            nx = int(rng.integers(6, 13)) * 10
+            p, f, _ = shock_bubble(nx=nx, ny=nx // 6, dx=0.003 * 600 / nx)
+            out.append(("shock_bubble", p, f))
+        elif kind == 3:
+            p, f, _ = couette(float(rng.uniform(0.3, 3.0)), nx=int(rng.integers(2, 80)),
+                              ny=int(rng.integers(couette_h[0], couette_h[1] + 1)),
+                              eq_version=int(rng.integers(1, 4)))
+            out.append(("couette2d", p, f))
+        elif kind == 4:
+            p, f = smooth_periodic(seed=int(rng.integers(0, 1 << 30)), nx=int(rng.integers(16, 200)),
+                                   ny=int(rng.integers(3, 70)), eq_version=int(rng.integers(1, 4)))
+            out.append(("periodic2d", p, f))
+        else:
+            N = int(rng.integers(max(129, riemann_n[0]), riemann_n[1] + 1))
+            p, f = smooth_periodic(seed=int(rng.integers(0, 1 << 30)), nx=N, ny=1, dx=1.0 / N, dt=1e-4)
+            out.append(("periodic_line", p, f))
+    return out
+
+
+# --------------------------------------------------------------------------
+# Uneven batch of independent 2-D shock/interface problems (random size,
+# Mach number, interface modes and Prandtl number per instance).
+# --------------------------------------------------------------------------
+def rm_batch(seed=0, n=96, nx=(128, 512), ny=(32, 128), pr_range=(0.3, 3.0)):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        p, f, _ = rm(seed=int(rng.integers(0, 1 << 30)), nx=int(rng.integers(nx[0], nx[1] + 1)),
+                     ny=int(rng.integers(ny[0], ny[1] + 1)), Pr=float(rng.uniform(*pr_range)))
+        out.append(("rm", p, f))
+    return out
+
+
+# --------------------------------------------------------------------------
 # Small smooth periodic states for invariants and wave tests.
 # --------------------------------------------------------------------------
 def smooth_periodic(seed=0, nx=32, ny=32, dx=0.01, dt=1e-4, s5=1e3, s7=1e3, s_other=2e3, amp=0.05,

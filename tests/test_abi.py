@@ -84,3 +84,22 @@ def test_batched_and_adjoint_forms_reject_the_limited_scheme():
     q = lbm.LbmParams.from_dict(p)
     assert autograd._lib().lbm_adjoint_workspace_bytes(ctypes.byref(q), 10, 0) == 0
     assert "scheme 0" in lbm.load().lbm_last_error().decode()
+
+
+def test_batch_workspace_covers_lines_and_tiled_instances():
+    """Host-side layout of the batched form: lines take 16 planes of their
+    length rounded to 16 nodes, tiled (2-D, or periodic lines over 128 nodes)
+    instances 16 planes of ny rows of nx rounded to 64 nodes; both arenas,
+    the tuner's backup and the descriptors must fit."""
+    from paper_1106_0785_amd import batch
+
+    items = inputs.mixed_batch(seed=2, n=12)
+    params = [p for _, p, _ in items]
+    need = 0
+    for p in params:
+        tiled = (p["nx"] > 1 and p["ny"] > 1) or (p["ny"] == 1 and p["bc"][0] == "periodic" and p["nx"] > 128)
+        need += 16 * 8 * (p["ny"] * ((p["nx"] + 63) // 64 * 64) if tiled else (p["nx"] * p["ny"] + 15) // 16 * 16)
+    got = batch.lbm_batch_workspace_bytes(params)
+    assert got >= 3 * need
+    assert got < 3 * need + 4 * 1024 * 1024
+    assert batch.lbm_batch_workspace_bytes([]) == 0

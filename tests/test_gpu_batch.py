@@ -110,3 +110,97 @@ def test_tuner_keeps_state_and_picks_a_schedule():
     assert np.array_equal(f0, f1)
     assert s["region"] in (128, 256)
     b.close()
+
+
+# ---------------------------------------------------------------------------
+# Batches mixing one-dimensional lines with two-dimensional (tiled) instances.
+# ---------------------------------------------------------------------------
+def _mixed(seed, n):
+    from paper_1106_0785_amd.batch import Batch
+
+    items = inputs.mixed_batch(seed=seed, n=n)
+    b = Batch([p for _, p, _ in items])
+    b.init([f for _, _, f in items])
+    return items, b
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b) / np.abs(b).max(axis=(1, 2), keepdims=True)))
+
+
+def test_mixed_batch_matches_single_problem_path_and_oracle():
+    """Every instance of a batch of lines, shock/interface and shock-bubble
+    set-ups, Couette channels, periodic states (three equilibrium versions)
+    and long periodic lines: tiled instances bitwise equal to the
+    single-problem kernel (same fused step), lines within rounding of it, and
+    moments of all within 1e-11 of the oracle. An odd step count leaves the
+    two kinds of instance in different buffers."""
+    items, b = _mixed(3, 18)
+    steps = 151
+    b.step(steps)
+    b.check()
+    fb = b.get_f().cpu().numpy()
+    kinds = set()
+    for i, (kind, p, fl) in enumerate(items):
+        _, gf = gpu_run(p, fl, steps)
+        fi = b.f_of(fb, i)
+        if p["nx"] > 1 and p["ny"] > 1 or kind == "periodic_line":
+            assert np.array_equal(fi, gf), (i, kind, _rel(fi, gf))
+        else:
+            assert _rel(fi, gf) <= 1e-12, (i, kind)
+        o, _ = oracle_run(p, fl, steps)
+        assert_parity(_moments_of(b, i), o, what="mixed instance %d (%s, %dx%d)" % (i, kind, p["nx"], p["ny"]))
+        kinds.add(kind)
+    assert {"rm", "shock_bubble", "couette2d", "periodic2d", "periodic_line"} <= kinds
+    b.close()
+
+
+def test_mixed_batch_budgets():
+    items, b = _mixed(8, 12)
+    budgets = [13 * (i + 1) + (i % 2) for i in range(len(items))]
+    b.set_budgets(budgets)
+    b.step(101)
+    fb = b.get_f().cpu().numpy()
+    m = {k: v.cpu().numpy() for k, v in b.moments().items()}
+    for i, (kind, p, fl) in enumerate(items):
+        n = min(101, budgets[i])
+        _, gf = gpu_run(p, fl, n)
+        assert _rel(b.f_of(fb, i), gf) <= 1e-12, (i, kind, budgets[i])
+        o, _ = oracle_run(p, fl, n)
+        assert_parity({k: b.split(v, i) for k, v in m.items()}, o, what="budget %d mixed instance %d" % (n, i))
+    b.close()
+
+
+def test_mixed_graph_replays_match_eager_runs():
+    import torch
+
+    items, g = _mixed(9, 12)
+    items, e = _mixed(9, 12)
+    g.set_schedule(256, 16, use_graph=True)
+    e.set_schedule(256, 16, use_graph=False)
+    for rep, k in enumerate((47, 47, 30, 47)):
+        g.step(k)
+        e.step(k)
+        torch.cuda.synchronize()
+        _ = torch.ones(1000, device="cuda").sum().item()
+        fg = g.get_f().cpu().numpy()
+        fe = e.get_f().cpu().numpy()
+        log("mixed graph replay %d (%d steps) bitwise equal to eager: %s" % (rep, k, np.array_equal(fg, fe)))
+        assert np.array_equal(fg, fe)
+    g.close()
+    e.close()
+
+
+def test_mixed_tuner_keeps_state():
+    items, b = _mixed(11, 12)
+    b.step(17)  # two line launches (h = 16), 17 tile steps: the kinds end in different buffers
+    f0 = b.get_f().cpu().numpy()
+    s = b.tune(probe_steps=16, use_cache=False)
+    f1 = b.get_f().cpu().numpy()
+    assert np.array_equal(f0, f1), s
+    b.step(5)
+    items2, r = _mixed(11, 12)
+    r.step(22)
+    assert np.array_equal(b.get_f().cpu().numpy(), r.get_f().cpu().numpy())
+    b.close()
+    r.close()

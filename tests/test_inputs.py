@@ -92,3 +92,21 @@ def test_shock_bubble_states_match_paper():
     # the shock sits between nodes 499 and 500 (the paper's 1-based [501, 600])
     assert rho[10, 497] < 1.05 and rho[10, 502] > 1.23
     assert m["radius"] == 20.0 and m["center"] == (449.0, 49.5)
+
+
+def test_mixed_and_2d_batches_are_seeded_and_shaped():
+    a = inputs.mixed_batch(seed=5, n=12)
+    b = inputs.mixed_batch(seed=5, n=12)
+    kinds = set()
+    for (ka, pa, fa), (kb, pb, fb) in zip(a, b):
+        assert ka == kb and pa == pb
+        for k in fa:
+            assert fa[k].shape == (pa["ny"], pa["nx"])
+            np.testing.assert_array_equal(fa[k], fb[k])
+        assert max(pa["s"]) * pa["dt"] <= 1.0 + 1e-12
+        kinds.add(ka)
+    assert {"rm", "shock_bubble", "couette2d", "periodic2d", "periodic_line"} <= kinds
+    assert {p["eq_version"] for _, p, _ in inputs.mixed_batch(seed=1, n=36)} == {1, 2, 3}
+    r = inputs.rm_batch(seed=0, n=8)
+    for kind, p, f in r:
+        assert 128 <= p["nx"] <= 512 and 32 <= p["ny"] <= 128 and f["rho"].shape == (p["ny"], p["nx"])
