@@ -126,7 +126,7 @@ def bench_batch(steps, seed=0, n=512, plain=True, two_d=False):
            "batched_gbps_equivalent": nodes * steps / tb * BYTES_PER_NODE / 1e9,
            "budgets_seconds": tbb, "budgets_node_steps": budget_node_steps,
            "budgets_mlups": budget_node_steps / tbb / 1e6,
-           "schedule": {k: sched[k] for k in ("region", "steps_per_launch", "chunks")}}
+           "schedule": {k: sched[k] for k in ("region", "steps_per_launch", "chunks", "tile_rows", "tiles")}}
     if not plain:
         return out
     sims = []

@@ -69,9 +69,17 @@ lbm_status lbm_batch_get_f(lbm_batch* b, double* d_f);
 lbm_status lbm_batch_set_schedule(lbm_batch* b, int32_t region, int32_t steps_per_launch, int32_t use_graph);
 lbm_status lbm_batch_get_schedule(const lbm_batch* b, int32_t* region, int32_t* steps_per_launch, int32_t* nchunks);
 
+/* Tile height of the tiled instances (rows per tile, a multiple of 4 in
+ * [4, 4096]; an instance shorter than that is one tile high). Results do not
+ * depend on it. ntiles = tiles per step over all tiled instances. */
+lbm_status lbm_batch_set_tile_rows(lbm_batch* b, int32_t rows);
+lbm_status lbm_batch_get_tile_rows(const lbm_batch* b, int32_t* rows, int32_t* ntiles);
+
 /* Autotuner: times every admissible (region, h) for probe_steps steps of the
- * line instances on the current state (synchronising the stream), restores
- * the state and keeps the fastest schedule; *best_ms receives its time. */
+ * line instances, then tile heights 8 ... 128 for probe_steps steps of the
+ * tiled instances, on the current state (synchronising the stream); restores
+ * the state and keeps the fastest of each; *best_ms receives the sum of the
+ * two best times. */
 lbm_status lbm_batch_tune(lbm_batch* b, int64_t probe_steps, double* best_ms);
 
 /* As lbm_check, for the batch. */

@@ -31,6 +31,9 @@ def _lib():
             "lbm_batch_get_f": ([P, P], ctypes.c_int),
             "lbm_batch_set_schedule": ([P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
             "lbm_batch_get_schedule": ([P] + [ctypes.POINTER(ctypes.c_int32)] * 3, ctypes.c_int),
+            "lbm_batch_set_tile_rows": ([P, ctypes.c_int32], ctypes.c_int),
+            "lbm_batch_get_tile_rows": ([P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
+                                        ctypes.c_int),
             "lbm_batch_tune": ([P, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
             "lbm_batch_check": ([P], ctypes.c_int),
             "lbm_batch_destroy": ([P], None),
@@ -148,6 +151,14 @@ class Batch:
         _check(_lib().lbm_batch_get_schedule(self.handle, ctypes.byref(r), ctypes.byref(h), ctypes.byref(c)))
         return {"region": r.value, "steps_per_launch": h.value, "chunks": c.value}
 
+    def set_tile_rows(self, rows):
+        _check(_lib().lbm_batch_set_tile_rows(self.handle, int(rows)))
+
+    def tile_rows(self):
+        r, t = ctypes.c_int32(), ctypes.c_int32()
+        _check(_lib().lbm_batch_get_tile_rows(self.handle, ctypes.byref(r), ctypes.byref(t)))
+        return {"tile_rows": r.value, "tiles": t.value}
+
     def tune(self, probe_steps=64, use_cache=True):
         """Run the library's autotuner (or reuse a cached choice for this batch
         signature and device). Returns the chosen schedule."""
@@ -160,13 +171,15 @@ class Batch:
                 cache = json.load(open(CACHE))
             except ValueError:
                 cache = {}
-        if use_cache and key in cache:
+        if use_cache and key in cache and "tile_rows" in cache[key]:
             c = cache[key]
             self.set_schedule(c["region"], c["steps_per_launch"])
+            self.set_tile_rows(c["tile_rows"])
             return dict(c, cached=True)
         best = ctypes.c_double()
         _check(_lib().lbm_batch_tune(self.handle, int(probe_steps), ctypes.byref(best)))
         s = self.schedule()
+        s.update(self.tile_rows())
         s["probe_ms"] = best.value
         if use_cache:
             os.makedirs(os.path.dirname(CACHE), exist_ok=True)

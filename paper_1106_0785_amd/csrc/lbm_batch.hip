@@ -53,7 +53,9 @@ struct lbm_batch {
   LineChunk* chunks;
   TileInst* tinsts;
   int* tile_inst;  // tile -> index in tinsts, grouped by (version, walls)
-  int ntiles;
+  int ntiles;      // tiles at the current tile height
+  int max_tiles;   // room in tile_inst (tiles at the smallest height)
+  int tile_rows;   // rows per tile of the tiled instances
   int tbegin[4][2], tend[4][2];
   int max_chunks;
   int* budget;
@@ -97,8 +99,8 @@ static int batch_tile_rows(const lbm_params* inst, int32_t n) {
 struct Layout {
   size_t arena_bytes, insts_off, chunks_off, tinsts_off, tiles_off, budget_off, flag_off, backup_off, total;
   long long arena_doubles;
-  int max_chunks, ntiled, ntiles;
-  int rows;  // rows per tile of the tiled instances
+  int max_chunks, ntiled, ntiles;  // ntiles: at the smallest tile height
+  int rows;  // default rows per tile of the tiled instances
   std::vector<long long> off;  // arena offset (doubles) of each instance
 };
 
@@ -128,7 +130,7 @@ static lbm_status layout_of(const lbm_params* inst, int32_t n, Layout* L) {
       dbl = (dbl + 63) / 64 * 64;  // 512-byte aligned rows
       L->off[i] = dbl;
       dbl += 16 * row_pitch(p.nx) * p.ny;
-      const MarchGeom g = march_geom(p.nx, p.ny, TileShape{L->rows, WAVES});
+      const MarchGeom g = march_geom(p.nx, p.ny, TileShape{WAVES, WAVES});  // most tiles any height gives
       ++ntiled;
       if ((long long)ntiles + g.ntiles > INT_MAX / 2) return fail(LBM_EINVAL, "batch has too many tiles");
       ntiles += g.ntiles;
@@ -184,14 +186,45 @@ static lbm_status build_chunks(lbm_batch* b, const Schedule& s) {
   return LBM_OK;
 }
 
+// Cuts the tiled instances into tiles of `rows` rows, builds the tile list
+// grouped by (equilibrium version, wall variant) and uploads descriptors and list.
+static lbm_status build_tiles(lbm_batch* b, int rows) {
+  std::vector<int> tiles;
+  for (TileInst& T : b->host_tinsts) T.geom = march_geom(T.nx, T.ny, TileShape{rows, WAVES});
+  for (int ver = 1; ver <= 3; ++ver)
+    for (int w = 0; w < 2; ++w) {
+      b->tbegin[ver][w] = (int)tiles.size();
+      for (size_t j = 0; j < b->host_tinsts.size(); ++j) {
+        const lbm_params& p = b->params[b->host_tinsts[j].gidx];
+        if (p.eq_version != ver || (int)has_walls(&p) != w) continue;
+        b->host_tinsts[j].first_tile = (int)tiles.size() - b->tbegin[ver][w];
+        for (int t = 0; t < b->host_tinsts[j].geom.ntiles; ++t) tiles.push_back((int)j);
+      }
+      b->tend[ver][w] = (int)tiles.size();
+    }
+  if ((long long)tiles.size() > b->max_tiles) return fail(LBM_EINVAL, "tile height needs more tiles than reserved");
+  hipError_t e = hipSuccess;
+  if (!b->host_tinsts.empty())
+    e = hipMemcpyAsync(b->tinsts, b->host_tinsts.data(), b->host_tinsts.size() * sizeof(TileInst),
+                       hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess && !tiles.empty())
+    e = hipMemcpyAsync(b->tile_inst, tiles.data(), tiles.size() * sizeof(int), hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);  // the host vectors are the copy sources
+  if (e != hipSuccess) return hip_fail(e, "uploading the tile list");
+  b->ntiles = (int)tiles.size();
+  b->tile_rows = rows;
+  drop_graphs(b);
+  return LBM_OK;
+}
+
 // Enqueues nsteps steps of every instance: the line instances as
 // ceil(nsteps / h) temporal-blocking launches starting from buffer
-// start_cur, the tiled instances (unless lines_only) as one launch per step
-// and group starting from buffer start_cur2.
+// start_cur, the tiled instances as one launch per step and group starting
+// from buffer start_cur2; `what` selects lines (1), tiled instances (2) or both.
 static hipError_t enqueue_steps(lbm_batch* b, int64_t nsteps, int start_cur, int start_cur2, hipStream_t stream,
-                                bool lines_only = false) {
+                                int what = 3) {
   int cur = start_cur;
-  const bool lines = b->vend[3] > b->vbegin[1];
+  const bool lines = (what & 1) && b->vend[3] > b->vbegin[1];
   for (int64_t n0 = 0; lines && n0 < nsteps; n0 += b->sched.h) {
     const int h = (int)std::min<int64_t>(b->sched.h, nsteps - n0);
     for (int ver = 1; ver <= 3; ++ver) {
@@ -220,7 +253,7 @@ static hipError_t enqueue_steps(lbm_batch* b, int64_t nsteps, int start_cur, int
     cur ^= 1;
   }
   int cur2 = start_cur2;
-  for (int64_t n = 0; !lines_only && b->ntiles > 0 && n < nsteps; ++n) {
+  for (int64_t n = 0; (what & 2) && b->ntiles > 0 && n < nsteps; ++n) {
     for (int ver = 1; ver <= 3; ++ver)
       for (int w = 0; w < 2; ++w) {
         const int nt = b->tend[ver][w] - b->tbegin[ver][w];
@@ -232,7 +265,8 @@ static hipError_t enqueue_steps(lbm_batch* b, int64_t nsteps, int start_cur, int
         else
           k = ver == 2 ? k_batch_tiles<2, false> : ver == 3 ? k_batch_tiles<3, false> : k_batch_tiles<1, false>;
         hipLaunchKernelGGL(k, dim3(8 * per_xcd), dim3(64 * WAVES), 0, stream, b->arena[cur2], b->arena[cur2 ^ 1],
-                           b->tinsts, b->tile_inst + b->tbegin[ver][w], nt, per_xcd, b->budget, (int)n, b->flag);
+                           b->tinsts, b->tile_inst + b->tbegin[ver][w], nt, per_xcd, b->budget, (int)n, (int)nsteps,
+                           b->flag);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
       }
@@ -279,7 +313,9 @@ lbm_status lbm_batch_create(const lbm_params* inst, int32_t n, void* d_workspace
   b->backup = (double*)(base + L.backup_off);
   b->max_chunks = L.max_chunks;
   b->arena_doubles = L.arena_doubles;
-  b->ntiles = L.ntiles;
+  b->ntiles = 0;
+  b->max_tiles = L.ntiles;
+  b->tile_rows = 0;
   b->cur = 0;
   b->cur2 = 0;
   b->use_graph = 1;
@@ -314,7 +350,6 @@ lbm_status lbm_batch_create(const lbm_params* inst, int32_t n, void* d_workspace
       T.nx = p.nx;
       T.ny = p.ny;
       T.gidx = i;
-      T.geom = march_geom(p.nx, p.ny, TileShape{L.rows, WAVES});
       make_coef(&p, &T.hot, &T.cold);
       b->host_tinsts.push_back(T);
       continue;
@@ -327,26 +362,8 @@ lbm_status lbm_batch_create(const lbm_params* inst, int32_t n, void* d_workspace
     make_coef(&p, &I.hot, &I.cold);
   }
   b->total_nodes = node;
-  // tile list grouped by (equilibrium version, wall variant)
-  std::vector<int> tiles;
-  for (int ver = 1; ver <= 3; ++ver)
-    for (int w = 0; w < 2; ++w) {
-      b->tbegin[ver][w] = (int)tiles.size();
-      for (size_t j = 0; j < b->host_tinsts.size(); ++j) {
-        const lbm_params& p = b->params[b->host_tinsts[j].gidx];
-        if (p.eq_version != ver || (int)has_walls(&p) != w) continue;
-        b->host_tinsts[j].first_tile = (int)tiles.size() - b->tbegin[ver][w];
-        for (int t = 0; t < b->host_tinsts[j].geom.ntiles; ++t) tiles.push_back((int)j);
-      }
-      b->tend[ver][w] = (int)tiles.size();
-    }
   std::vector<int> budget(n, INT_MAX);
   hipError_t e = hipMemcpyAsync(b->insts, b->host_insts.data(), n * sizeof(LineInst), hipMemcpyHostToDevice, b->stream);
-  if (e == hipSuccess && !b->host_tinsts.empty())
-    e = hipMemcpyAsync(b->tinsts, b->host_tinsts.data(), b->host_tinsts.size() * sizeof(TileInst),
-                       hipMemcpyHostToDevice, b->stream);
-  if (e == hipSuccess && !tiles.empty())
-    e = hipMemcpyAsync(b->tile_inst, tiles.data(), tiles.size() * sizeof(int), hipMemcpyHostToDevice, b->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(b->budget, budget.data(), n * sizeof(int), hipMemcpyHostToDevice, b->stream);
   if (e == hipSuccess) e = hipMemsetAsync(b->flag, 0, 256, b->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
@@ -356,6 +373,7 @@ lbm_status lbm_batch_create(const lbm_params* inst, int32_t n, void* d_workspace
     return hip_fail(e, "uploading the batch description");
   }
   st = build_chunks(b, Schedule{256, 16});
+  if (st == LBM_OK) st = build_tiles(b, L.rows);
   if (st != LBM_OK) {
     (void)hipStreamDestroy(b->capture);
     delete b;
@@ -548,9 +566,9 @@ lbm_status lbm_batch_tune(lbm_batch* b, int64_t probe_steps, double* best_ms) {
       if (!schedule_ok(s)) continue;
       if (build_chunks(b, s) != LBM_OK) continue;
       // warm-up + timed trial, both without graphs
-      e = enqueue_steps(b, std::min<int64_t>(probe_steps, 2 * h), b->cur, b->cur2, b->stream, true);
+      e = enqueue_steps(b, std::min<int64_t>(probe_steps, 2 * h), b->cur, b->cur2, b->stream, 1);
       if (e == hipSuccess) e = hipEventRecord(t0, b->stream);
-      if (e == hipSuccess) e = enqueue_steps(b, probe_steps, b->cur, b->cur2, b->stream, true);
+      if (e == hipSuccess) e = enqueue_steps(b, probe_steps, b->cur, b->cur2, b->stream, 1);
       if (e == hipSuccess) e = hipEventRecord(t1, b->stream);
       if (e == hipSuccess) e = hipEventSynchronize(t1);
       if (e != hipSuccess) break;
@@ -572,8 +590,66 @@ lbm_status lbm_batch_tune(lbm_batch* b, int64_t probe_steps, double* best_ms) {
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) return hip_fail(e, "tuning run");
   b->cur = saved_cur;
-  if (best_ms) *best_ms = best_t;
-  return build_chunks(b, best);
+  lbm_status st = build_chunks(b, best);
+  if (st != LBM_OK) return st;
+  if (b->host_tinsts.empty()) {
+    if (best_ms) *best_ms = best_t;
+    return LBM_OK;
+  }
+  // tile height of the tiled instances, timed the same way on their state
+  const int saved_cur2 = b->cur2;
+  t0 = t1 = nullptr;
+  e = hipMemcpyAsync(b->backup, b->arena[saved_cur2], bytes, hipMemcpyDeviceToDevice, b->stream);
+  if (e == hipSuccess) e = hipEventCreate(&t0);
+  if (e == hipSuccess) e = hipEventCreate(&t1);
+  if (e != hipSuccess) {
+    if (t0) (void)hipEventDestroy(t0);
+    return hip_fail(e, "backing up the state");
+  }
+  int best_rows = b->tile_rows;
+  float best_tt = 1e30f;
+  const int heights[5] = {8, 16, 32, 64, 128};
+  for (int rows : heights) {
+    if (build_tiles(b, rows) != LBM_OK) continue;
+    e = enqueue_steps(b, 2, saved_cur2, saved_cur2, b->stream, 2);
+    if (e == hipSuccess) e = hipEventRecord(t0, b->stream);
+    if (e == hipSuccess) e = enqueue_steps(b, probe_steps, saved_cur2, saved_cur2, b->stream, 2);
+    if (e == hipSuccess) e = hipEventRecord(t1, b->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(t1);
+    if (e != hipSuccess) break;
+    float ms = 0;
+    e = hipEventElapsedTime(&ms, t0, t1);
+    if (e != hipSuccess) break;
+    if (ms < best_tt) {
+      best_tt = ms;
+      best_rows = rows;
+    }
+    e = hipMemcpyAsync(b->arena[saved_cur2], b->backup, bytes, hipMemcpyDeviceToDevice, b->stream);
+    if (e != hipSuccess) break;
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  if (e == hipSuccess) e = hipMemcpyAsync(b->arena[saved_cur2], b->backup, bytes, hipMemcpyDeviceToDevice, b->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(b->flag, 0, sizeof(int), b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return hip_fail(e, "tuning run");
+  b->cur2 = saved_cur2;
+  if (best_ms) *best_ms = best_t + best_tt;
+  return build_tiles(b, best_rows);
+}
+
+lbm_status lbm_batch_set_tile_rows(lbm_batch* b, int32_t rows) {
+  if (!b) return fail(LBM_EINVAL, "batch is NULL");
+  if (rows < WAVES || rows > 4096 || rows % WAVES)
+    return fail(LBM_EINVAL, "tile rows must be a multiple of %d in [%d, 4096]", WAVES, WAVES);
+  return build_tiles(b, rows);
+}
+
+lbm_status lbm_batch_get_tile_rows(const lbm_batch* b, int32_t* rows, int32_t* ntiles) {
+  if (!b) return fail(LBM_EINVAL, "batch is NULL");
+  if (rows) *rows = b->tile_rows;
+  if (ntiles) *ntiles = b->ntiles;
+  return LBM_OK;
 }
 
 lbm_status lbm_batch_check(lbm_batch* b) {

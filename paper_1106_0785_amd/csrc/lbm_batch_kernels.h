@@ -189,13 +189,16 @@ struct TileInst {
 // One time step of every tile of a group of tile instances (same
 // equilibrium version and wall variant); workgroup b takes tile
 // (b mod 8) per_xcd + b / 8 of the group's list, so each XCD gets a
-// contiguous run. An instance whose budget is spent copies its tile through.
+// contiguous run. An instance whose budget b is spent (step n >= b of a call
+// of nsteps steps) idles: its final state stays where step b - 1 put it, and
+// at n == b it is copied across once if the remaining nsteps - b steps are
+// odd, so that after the call it sits in the same buffer as everyone else's.
 template <int VER, bool WALLS>
 __global__ __launch_bounds__(64 * WAVES, 2) void k_batch_tiles(const double* __restrict__ A, double* __restrict__ B,
                                                                 const TileInst* __restrict__ insts,
                                                                 const int* __restrict__ tile_inst, int ntiles,
                                                                 int per_xcd, const int* __restrict__ budget, int n,
-                                                                int* flag) {
+                                                                int nsteps, int* flag) {
   const int t = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
   if (t >= ntiles) return;  // whole workgroup leaves together
   const TileInst& I = insts[tile_inst[t]];
@@ -207,7 +210,9 @@ __global__ __launch_bounds__(64 * WAVES, 2) void k_batch_tiles(const double* __r
   F.pitch = I.pitch;
   F.plane = I.plane;
   const int tile = t - I.first_tile;
-  if (budget[I.gidx] <= n) {
+  const int bud = budget[I.gidx];
+  if (bud <= n) {
+    if (n != bud || ((nsteps - bud) & 1) == 0) return;
     const int strip = tile % I.geom.nstrips, seg = tile / I.geom.nstrips;
     const int x = strip * STRIP + (threadIdx.x & 63);
     const int y1 = min((seg + 1) * I.geom.rows, I.ny);

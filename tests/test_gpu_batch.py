@@ -204,3 +204,24 @@ def test_mixed_tuner_keeps_state():
     assert np.array_equal(b.get_f().cpu().numpy(), r.get_f().cpu().numpy())
     b.close()
     r.close()
+
+
+@pytest.mark.parametrize("rows", [4, 8, 64, 128])
+def test_mixed_tile_heights_agree(rows):
+    """Tile height of the tiled instances changes the work split, not the
+    result (bitwise), also with budgets."""
+    items, b = _mixed(13, 12)
+    items, r = _mixed(13, 12)
+    budgets = [7 * (i + 2) for i in range(len(items))]
+    b.set_budgets(budgets)
+    r.set_budgets(budgets)
+    b.set_tile_rows(rows)
+    info = b.tile_rows()
+    assert info["tile_rows"] == rows and info["tiles"] > 0
+    b.step(61)
+    r.step(61)
+    f, ref = b.get_f().cpu().numpy(), r.get_f().cpu().numpy()
+    log("tile rows %d (%d tiles) vs default %s: bitwise %s" % (rows, info["tiles"], r.tile_rows(), np.array_equal(f, ref)))
+    assert np.array_equal(f, ref)
+    b.close()
+    r.close()
