@@ -11,6 +11,7 @@ from .oracle import (  # noqa: F401
     lib_path,
     matrices,
     feq_moments,
+    node_equilibrium_complex,
     init,
     moments,
     run,

@@ -613,6 +613,32 @@ int oracle_feq_moments(int version, double rho, double ux, double uy, double T, 
   return 0;
 }
 
+// For one node's distributions f (16 complex values): the equilibrium
+// moments f^eq_1..16 and (rho, u_x, u_y, T), through the same moment and
+// macroscopic steps as the time step (complex, so that a complex-step
+// perturbation of f yields their derivatives with respect to f).
+int oracle_node_equilibrium_complex(int version, const double* f_re, const double* f_im, double* q_re, double* q_im,
+                                    double* mac) {
+  build_tables();
+  if (version < 1 || version > 3) return -1;
+  using C = std::complex<double>;
+  C f[NQ], fh[NQ], q[NQ];
+  for (int i = 0; i < NQ; ++i) f[i] = C(f_re[i], f_im[i]);
+  to_moments(f, fh);
+  Macro<C> m = macro_of(fh);
+  feq_moments(version, m, q);
+  for (int k = 0; k < NQ; ++k) {
+    q_re[k] = q[k].real();
+    q_im[k] = q[k].imag();
+  }
+  const C v[4] = {m.rho, m.ux, m.uy, m.T};
+  for (int k = 0; k < 4; ++k) {
+    mac[2 * k] = v[k].real();
+    mac[2 * k + 1] = v[k].imag();
+  }
+  return 0;
+}
+
 // f = M^-1 f^eq(rho, u, T) at every node; fields [ny][nx], f [16][ny][nx].
 int oracle_init(const oracle_params* p, const double* rho, const double* ux, const double* uy, const double* T,
                 double* f) {

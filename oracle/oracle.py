@@ -85,6 +85,7 @@ def _load(variant="plain"):
         pp = ctypes.POINTER(OracleParams)
         lib.oracle_matrices.argtypes = [P, P, P]
         lib.oracle_feq_moments.argtypes = [ctypes.c_int] + [ctypes.c_double] * 4 + [P]
+        lib.oracle_node_equilibrium_complex.argtypes = [ctypes.c_int, P, P, P, P, P]
         lib.oracle_init.argtypes = [pp, P, P, P, P, P]
         lib.oracle_moments.argtypes = [pp, P, P, P, P, P, P]
         lib.oracle_run.argtypes = [pp, P, ctypes.c_int64, P, ctypes.c_int]
@@ -131,6 +132,17 @@ def feq_moments(version, rho, ux, uy, T):
     if rc:
         raise ValueError("oracle_feq_moments rejected its arguments")
     return out
+
+
+def node_equilibrium_complex(version, f):
+    """For one node's complex distributions f (16): (complex f^eq moments
+    [16], complex (rho, u_x, u_y, T))."""
+    f = np.asarray(f, dtype=np.complex128)
+    fr, fi = _f64(f.real), _f64(f.imag)
+    qr, qi, mac = np.zeros(16), np.zeros(16), np.zeros(8)
+    if _load().oracle_node_equilibrium_complex(int(version), _ptr(fr), _ptr(fi), _ptr(qr), _ptr(qi), _ptr(mac)):
+        raise ValueError("oracle_node_equilibrium_complex rejected its arguments")
+    return qr + 1j * qi, mac[0::2] + 1j * mac[1::2]
 
 
 def init(p, rho, ux, uy, T):

@@ -1,0 +1,111 @@
+"""Pins of the oracle's von Neumann amplification matrix (Sec. III).
+
+  * Brute force: on a periodic grid, one step of the oracle's own time step,
+    differentiated by complex step about a uniform state, maps the Fourier
+    mode v e^{i theta.x} to e^{i theta.x} G(theta) v at every node (all
+    three equilibrium versions, modified and unmodified models, moving base
+    states so that the modification terms are active).
+  * theta = 0 closed form: the spectrum is {1 (x4)} and {1 - dt s_k, k >= 5}
+    (the conserved moments do not relax; the equilibria depend on them only).
+  * Lax-Wendroff symbol: with the relaxation rates tending to zero only the
+    diagonal convection symbol is left, of modulus
+    sqrt(1 - 4 c^2 (1 - c^2) sin^4(theta/2)) per axis.
+  * The paper's case (a) (Fig. 2: rho, u, T = 2, 2, 0, 2, every s = 1e5,
+    dx = dy = 1e-3, dt = 1e-5) is stable: |omega|_max = 1 at theta = 0 and
+    never above 1 across the sweep.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import stability as so
+from paper_1106_0785_amd import inputs
+
+H = 1e-30
+
+
+def _params(version=1, modified=1, s=None, dx=0.01, dy=0.012, dt=1e-4):
+    if s is None:
+        rng = np.random.default_rng(version * 10 + modified)
+        s = list(rng.uniform(1e3, 6e3, size=16))
+    return inputs.params(1, 1, dx, dy, dt, s, ["periodic"] * 4, eq_version=version, modified=modified)
+
+
+def _step_jacobian_on_mode(p, state, v, mx, my, nx=8, ny=6):
+    """(J w)[16, ny, nx] for w = v e^{i theta.x} on an nx x ny periodic grid,
+    theta = 2 pi (mx / nx, my / ny), J = the oracle step's Jacobian at the
+    uniform state (complex step along Re w and Im w)."""
+    q = dict(p, nx=nx, ny=ny, bc=["periodic"] * 4)
+    fields = {k: np.full((ny, nx), float(x)) for k, x in zip(("rho", "ux", "uy", "T"), state)}
+    f0 = oracle.init(q, **fields)
+    X, Y = np.meshgrid(np.arange(nx), np.arange(ny))
+    phase = np.exp(1j * (2 * np.pi * mx / nx * X + 2 * np.pi * my / ny * Y))
+    w = v[:, None, None] * phase[None]
+    out = []
+    for part in (w.real, w.imag):
+        r = oracle.run_complex(q, f0 + 1j * H * part, 1, nthreads=1)
+        out.append(r.imag / H)
+    return out[0] + 1j * out[1], phase
+
+
+@pytest.mark.parametrize("version,modified", [(1, 1), (1, 0), (2, 1), (3, 1), (1, 2), (3, 0)])
+def test_matrix_equals_the_step_jacobian_on_fourier_modes(version, modified):
+    p = _params(version, modified)
+    state = (1.3, 0.35, -0.25, 1.1)
+    rng = np.random.default_rng(7)
+    for mx, my in ((3, 1), (1, 0), (0, 2), (5, 3)):
+        v = rng.normal(size=16) + 1j * rng.normal(size=16)
+        jw, phase = _step_jacobian_on_mode(p, state, v, mx, my)
+        G = so.amplification_matrix(p, state, 2 * np.pi * mx / 8, 2 * np.pi * my / 6)
+        want = (G @ v)[:, None, None] * phase[None]
+        err = np.max(np.abs(jw - want)) / np.max(np.abs(want))
+        assert err < 1e-12, (mx, my, err)
+
+
+def test_modification_changes_the_matrix_only_through_moving_states():
+    s = list(np.random.default_rng(3).uniform(1e3, 6e3, size=16))
+    st = (1.3, 0.35, -0.25, 1.1)
+    a = so.amplification_matrix(_params(1, 1, s=s), st, 0.7, 0.4)
+    b = so.amplification_matrix(_params(1, 0, s=s), st, 0.7, 0.4)
+    assert np.max(np.abs(a - b)) > 1e-6
+    rest = (1.3, 0.0, 0.0, 1.1)
+    a = so.amplification_matrix(_params(1, 1, s=s), rest, 0.7, 0.4)
+    b = so.amplification_matrix(_params(1, 0, s=s), rest, 0.7, 0.4)
+    assert np.max(np.abs(a - b)) == 0.0
+
+
+@pytest.mark.parametrize("version", [1, 2, 3])
+def test_spectrum_at_zero_wavenumber(version):
+    p = _params(version, 1)
+    G = so.amplification_matrix(p, (0.8, 0.4, 0.1, 0.9), 0.0, 0.0)
+    ev = np.sort_complex(np.linalg.eigvals(G))
+    want = np.sort_complex(np.array([1.0] * 4 + [1.0 - p["dt"] * s for s in p["s"][4:]], dtype=complex))
+    assert np.max(np.abs(ev - want)) < 1e-11
+
+
+def test_lax_wendroff_symbol_remains_without_relaxation():
+    s = [1e-9] * 16
+    p = _params(1, 0, s=s, dx=0.01, dy=0.02, dt=2e-3)
+    V, _, _ = oracle.matrices()
+    for tx, ty in ((0.3, 0.0), (1.7, 2.9), (np.pi, np.pi / 2)):
+        G = so.amplification_matrix(p, (1.0, 0.2, 0.1, 1.0), tx, ty)
+        assert np.max(np.abs(G - np.diag(np.diag(G)))) < 1e-8
+        for i in range(16):
+            cx, cy = V[i, 0] * 0.2, V[i, 1] * 0.1
+            sym = 1 - 1j * cx * np.sin(tx) + cx * cx * (np.cos(tx) - 1) - 1j * cy * np.sin(ty) + cy * cy * (np.cos(ty) - 1)
+            assert abs(G[i, i] - sym) < 1e-8
+    # one axis alone: the textbook Lax-Wendroff amplification factor
+    G = so.amplification_matrix(p, (1.0, 0.0, 0.0, 1.0), 1.1, 0.0)
+    for i in range(16):
+        c = V[i, 0] * 0.2
+        assert abs(abs(G[i, i]) - np.sqrt(1 - 4 * c * c * (1 - c * c) * np.sin(1.1 / 2) ** 4)) < 1e-8
+
+
+def test_paper_case_a_is_stable():
+    p = _params(1, 1, s=[1e5] * 16, dx=1e-3, dy=1e-3, dt=1e-5)
+    th = np.linspace(0.0, np.pi, 41)
+    w = so.omega_max(p, (2.0, 2.0, 0.0, 2.0), np.stack([th, np.zeros_like(th)], axis=1))
+    assert abs(w[0] - 1.0) < 1e-12
+    assert np.all(w <= 1.0 + 1e-12)
+    assert np.all(w[1:] < 1.0)
