@@ -11,6 +11,7 @@ from .oracle import (  # noqa: F401
     lib_path,
     matrices,
     feq_moments,
+    feq_moments_complex,
     node_equilibrium_complex,
     init,
     moments,

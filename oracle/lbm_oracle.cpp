@@ -639,6 +639,30 @@ int oracle_node_equilibrium_complex(int version, const double* f_re, const doubl
   return 0;
 }
 
+// Equilibrium moments f^eq_1..16 at one complex state (rho, u_x, u_y, T)
+// ([4] real and imaginary parts), so that a complex-step perturbation of one
+// of them yields the derivatives with respect to it.
+int oracle_feq_moments_complex(int version, const double* v_re, const double* v_im, double* q_re, double* q_im) {
+  build_tables();
+  if (version < 1 || version > 3) return -1;
+  using C = std::complex<double>;
+  Macro<C> m;
+  m.rho = C(v_re[0], v_im[0]);
+  m.ux = C(v_re[1], v_im[1]);
+  m.uy = C(v_re[2], v_im[2]);
+  m.T = C(v_re[3], v_im[3]);
+  m.jx = m.rho * m.ux;
+  m.jy = m.rho * m.uy;
+  m.e = m.rho * (m.T + (m.ux * m.ux + m.uy * m.uy) / 2.0);
+  C q[NQ];
+  feq_moments(version, m, q);
+  for (int k = 0; k < NQ; ++k) {
+    q_re[k] = q[k].real();
+    q_im[k] = q[k].imag();
+  }
+  return 0;
+}
+
 // f = M^-1 f^eq(rho, u, T) at every node; fields [ny][nx], f [16][ny][nx].
 int oracle_init(const oracle_params* p, const double* rho, const double* ux, const double* uy, const double* T,
                 double* f) {

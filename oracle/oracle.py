@@ -86,6 +86,7 @@ def _load(variant="plain"):
         lib.oracle_matrices.argtypes = [P, P, P]
         lib.oracle_feq_moments.argtypes = [ctypes.c_int] + [ctypes.c_double] * 4 + [P]
         lib.oracle_node_equilibrium_complex.argtypes = [ctypes.c_int, P, P, P, P, P]
+        lib.oracle_feq_moments_complex.argtypes = [ctypes.c_int, P, P, P, P]
         lib.oracle_init.argtypes = [pp, P, P, P, P, P]
         lib.oracle_moments.argtypes = [pp, P, P, P, P, P, P]
         lib.oracle_run.argtypes = [pp, P, ctypes.c_int64, P, ctypes.c_int]
@@ -143,6 +144,16 @@ def node_equilibrium_complex(version, f):
     if _load().oracle_node_equilibrium_complex(int(version), _ptr(fr), _ptr(fi), _ptr(qr), _ptr(qi), _ptr(mac)):
         raise ValueError("oracle_node_equilibrium_complex rejected its arguments")
     return qr + 1j * qi, mac[0::2] + 1j * mac[1::2]
+
+
+def feq_moments_complex(version, state):
+    """Equilibrium moments [16] (complex) at a complex state (rho, u_x, u_y, T)."""
+    v = np.asarray(state, dtype=np.complex128)
+    vr, vi = _f64(v.real), _f64(v.imag)
+    qr, qi = np.zeros(16), np.zeros(16)
+    if _load().oracle_feq_moments_complex(int(version), _ptr(vr), _ptr(vi), _ptr(qr), _ptr(qi)):
+        raise ValueError("oracle_feq_moments_complex rejected its arguments")
+    return qr + 1j * qi
 
 
 def init(p, rho, ux, uy, T):

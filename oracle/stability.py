@@ -18,10 +18,11 @@ times itself. G is the sum of
     the symbol (e^{i t} - e^{-i t}) / (2 dx) (reading of the paper's silent
     gradient discretisation: the step's own central differences).
 
-The derivatives d f^eq / d f and d u / d f come from the oracle's own
-moment, macroscopic and equilibrium steps by complex-step differentiation
-(no subtraction, exact to rounding). |omega|_max is the largest modulus
-among numpy's eigenvalues of G.
+The derivative d f^eq / d f follows the paper's chain rule through (rho,
+u, T): the oracle's equilibrium moments differentiated by complex step (no
+subtraction, exact to rounding) at the state itself, times the derivatives
+of (rho, u, T) with respect to f from their definitions. |omega|_max is the
+largest modulus among numpy's eigenvalues of G.
 """
 
 import numpy as np
@@ -31,27 +32,25 @@ from . import oracle
 H = 1e-30  # complex step
 
 
-def _base(p, state):
-    """Distributions of the uniform state: M^-1 f^eq(rho, u, T)."""
-    q = dict(p, nx=1, ny=1, bc=["periodic"] * 4)
-    rho, ux, uy, T = (np.full((1, 1), float(v)) for v in state)
-    return oracle.init(q, rho, ux, uy, T)[:, 0, 0]
-
-
 def derivatives(p, state):
     """(d f^eq_k / d f_j [16, 16], d u_x / d f_j [16], d u_y / d f_j [16]) at
-    the uniform state."""
-    f0 = _base(p, state)
-    jeq = np.zeros((16, 16))
-    dux = np.zeros(16)
-    duy = np.zeros(16)
-    for j in range(16):
-        f = f0.astype(np.complex128)
-        f[j] += 1j * H
-        q, mac = oracle.node_equilibrium_complex(p["eq_version"], f)
-        jeq[:, j] = q.imag / H
-        dux[j] = mac[1].imag / H
-        duy[j] = mac[2].imag / H
+    the uniform state, by the chain rule of Sec. III through rho, u and T:
+    the derivatives of the equilibrium moments with respect to (rho, u_x,
+    u_y, T) by complex step at the state itself, and those of (rho, u, T)
+    with respect to f from their definitions rho = sum f, rho u = sum f v,
+    rho (T + u^2/2) = sum f v^2/2 (moment rows 1..4 of M)."""
+    _, M, _ = oracle.matrices()
+    rho, ux, uy, T = (float(v) for v in state)
+    dq = np.zeros((16, 4))
+    for c in range(4):
+        v = np.array([rho, ux, uy, T], dtype=np.complex128)
+        v[c] += 1j * H
+        dq[:, c] = oracle.feq_moments_complex(p["eq_version"], v).imag / H
+    drho = M[0]
+    dux = (M[1] - ux * M[0]) / rho
+    duy = (M[2] - uy * M[0]) / rho
+    dT = (M[3] - (T + 0.5 * (ux * ux + uy * uy)) * M[0]) / rho - ux * dux - uy * duy
+    jeq = np.outer(dq[:, 0], drho) + np.outer(dq[:, 1], dux) + np.outer(dq[:, 2], duy) + np.outer(dq[:, 3], dT)
     return jeq, dux, duy
 
 

@@ -109,3 +109,21 @@ def test_paper_case_a_is_stable():
     assert abs(w[0] - 1.0) < 1e-12
     assert np.all(w <= 1.0 + 1e-12)
     assert np.all(w[1:] < 1.0)
+
+
+@pytest.mark.parametrize("version", [1, 2, 3])
+def test_chain_rule_matches_differentiating_the_node_path(version):
+    """d f^eq / d f by the chain rule at the state equals the complex-step
+    derivative through the step's own moment and macroscopic computation
+    (f -> f^ -> rho, u, T -> f^eq) at the distributions of that state."""
+    p = _params(version, 1)
+    st = (1.3, 0.35, -0.25, 1.1)
+    jeq, dux, duy = so.derivatives(p, st)
+    q = dict(p, nx=1, ny=1)
+    f0 = oracle.init(q, *(np.full((1, 1), v) for v in st))[:, 0, 0]
+    for j in range(16):
+        f = f0.astype(np.complex128)
+        f[j] += 1j * H
+        qq, mac = oracle.node_equilibrium_complex(version, f)
+        assert np.max(np.abs(qq.imag / H - jeq[:, j])) <= 1e-12 * max(1.0, np.max(np.abs(jeq)))
+        assert abs(mac[1].imag / H - dux[j]) < 1e-13 and abs(mac[2].imag / H - duy[j]) < 1e-13
