@@ -22,7 +22,8 @@ The derivative d f^eq / d f follows the paper's chain rule through (rho,
 u, T): the oracle's equilibrium moments differentiated by complex step (no
 subtraction, exact to rounding) at the state itself, times the derivatives
 of (rho, u, T) with respect to f from their definitions. |omega|_max is the
-largest modulus among numpy's eigenvalues of G.
+largest modulus among numpy's eigenvalues of G (taken in the moment basis,
+see radius()).
 """
 
 import numpy as np
@@ -85,8 +86,14 @@ def amplification_matrix(p, state, theta_x, theta_y, derivs=None):
 
 
 def radius(G):
-    """|omega|_max: the largest eigenvalue modulus of G."""
-    return float(np.max(np.abs(np.linalg.eigvals(G))))
+    """|omega|_max: the largest eigenvalue modulus of G (velocity basis).
+    The eigenvalues are taken of the similar matrix M G M^-1 (the oracle's
+    M and M^-1): the same spectrum, but far less non-normal for these
+    operators (the collision acts moment by moment), so numpy's
+    double-precision eigenvalues are several times closer to exact ones
+    (checked against 40-digit eigenvalues)."""
+    _, M, Mi = oracle.matrices()
+    return float(np.max(np.abs(np.linalg.eigvals(M @ G @ Mi))))
 
 
 def omega_max(p, state, thetas):
