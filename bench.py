@@ -209,6 +209,46 @@ def traffic_from_profiles(kernel_name, workload):
     return None
 
 
+STAB_FLOPS_PER_SQUARING = 4 * 2 * 16 ** 3  # complex 16x16 product as four real ones
+
+
+def bench_stability(n=512, squarings=48, reps=5, cpu_points=400):
+    """Von Neumann map of the paper's Fig. 2 cases (a)-(d): |omega|_max on an
+    n x n wavenumber grid over [0, pi]^2 per case (squarings of G on the FP64
+    matrix cores), against the oracle's eigenvalues on a sample of points."""
+    import torch
+
+    import oracle.stability as so
+    from paper_1106_0785_amd import inputs, stability
+
+    params, states = inputs.fig2_stability_sets((1,))
+    th_h = inputs.wavenumber_grid(n)
+    th = torch.tensor(th_h, device="cuda")
+    stability.omega_max(params, states, th, squarings)  # warm-up
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        r = stability.omega_max(params, states, th, squarings)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) / 1e3)
+    t = sorted(ts)[len(ts) // 2]
+    pts = len(params) * th_h.shape[0]
+    flops = pts * squarings * STAB_FLOPS_PER_SQUARING
+    out = {"sets": len(params), "points": pts, "squarings": squarings, "seconds": t, "points_per_s": pts / t,
+           "tflops": flops / t / 1e12, "mfma_fp64_frac": flops / t / 78.6e12,
+           "max_omega": [float(v) for v in r.max(dim=1).values.cpu()]}
+    idx = np.random.default_rng(0).integers(0, th_h.shape[0], size=cpu_points // len(params))
+    t0 = time.perf_counter()
+    for k in range(len(params)):
+        so.omega_max(params[k], states[k], th_h[idx])
+    tc = time.perf_counter() - t0
+    out["cpu_oracle_points_per_s"] = len(params) * len(idx) / tc
+    return out
+
+
 def copy_ceiling(nx, ny, reps=20):
     """Bandwidth of two plain copies of the distribution layout, as context
     for the roofline: the library's streaming probe (the step kernel's access
@@ -268,7 +308,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--quick", action="store_true", help="headline workload only")
-    ap.add_argument("--only", choices=["batch", "batch2d", "adjoint", "limited"], help="run one side measurement alone and print "
+    ap.add_argument("--only", choices=["batch", "batch2d", "adjoint", "limited", "stability"], help="run one side measurement alone and print "
                     "its JSON (for profiling; not the benchmark line)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -290,6 +330,9 @@ def main():
         return
     if args.only == "adjoint":
         print(json.dumps(bench_adjoint()), flush=True)
+        return
+    if args.only == "stability":
+        print(json.dumps(bench_stability(reps=2, cpu_points=8)), flush=True)
         return
     if args.only == "limited":
         pl, fll, _ = inputs.rm(seed=0, nx=4096, ny=1024, width_cells=0.5)
@@ -323,6 +366,8 @@ def main():
         extra["batch_rm2d_96"] = bench_batch(200, n=96, two_d=True)
         log("adjoint rm 512x128, 2000 steps")
         extra["adjoint_rm_512x128"] = bench_adjoint()
+        log("stability map: Fig. 2 cases, 512 x 512 wavenumbers")
+        extra["stability_fig2_512x512"] = bench_stability()
 
     log("copy ceiling")
     extra["copy_ceiling_%dx%d" % (nx, ny)] = copy_ceiling(nx, ny)

@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = ["lbm_api.hip", "lbm_batch.hip", "lbm_adjoint.hip"]
+SOURCES = ["lbm_api.hip", "lbm_batch.hip", "lbm_adjoint.hip", "lbm_stability.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -347,6 +347,44 @@ def rm_batch(seed=0, n=96, nx=(128, 512), ny=(32, 128), pr_range=(0.3, 3.0)):
 
 
 # --------------------------------------------------------------------------
+# Von Neumann stability cases of Fig. 2 (Sec. III): base state (rho, u_x,
+# u_y, T), dx = dy = 1e-3, dt = 1e-5, relaxation rates 1e5 except those
+# listed (1-based index) for the paper's model ("three versions").
+# --------------------------------------------------------------------------
+FIG2_CASES = {
+    "a": ((2.0, 2.0, 0.0, 2.0), {}),
+    "b": ((2.0, 6.0, 0.0, 2.0), {9: 1e3}),
+    "c": ((2.0, 10.0, 0.0, 2.0), {9: 1.2e4, 13: 1e2, 14: 5e4, 15: 1.5e3}),
+    "d": ((2.0, 12.0, 0.0, 2.0), {9: 1e4, 13: 1e2, 14: 6e4, 15: 1.5e3}),
+}
+
+
+def fig2_stability_sets(versions=(1,), modified=1):
+    """(params list, base-state list) for cases (a)-(d), each under every
+    equilibrium version given."""
+    params, states = [], []
+    for case, (st, over) in FIG2_CASES.items():
+        s = [1e5] * 16
+        for k, v in over.items():
+            s[k - 1] = v
+        for ver in versions:
+            params.append(params_of_stability(s, ver, modified))
+            states.append(st)
+    return params, states
+
+
+def params_of_stability(s, version=1, modified=1, dx=1e-3, dy=1e-3, dt=1e-5):
+    return params(1, 1, dx, dy, dt, s, ["periodic"] * 4, eq_version=version, modified=modified)
+
+
+def wavenumber_grid(n, lo=0.0, hi=math.pi):
+    """[n*n, 2] grid of (theta_x, theta_y) over [lo, hi]^2, theta_x fastest."""
+    g = np.linspace(lo, hi, n)
+    tx, ty = np.meshgrid(g, g)
+    return np.stack([tx.ravel(), ty.ravel()], 1)
+
+
+# --------------------------------------------------------------------------
 # Small smooth periodic states for invariants and wave tests.
 # --------------------------------------------------------------------------
 def smooth_periodic(seed=0, nx=32, ny=32, dx=0.01, dt=1e-4, s5=1e3, s7=1e3, s_other=2e3, amp=0.05,

@@ -103,3 +103,47 @@ def test_batch_workspace_covers_lines_and_tiled_instances():
     assert got >= 3 * need
     assert got < 3 * need + 4 * 1024 * 1024
     assert batch.lbm_batch_workspace_bytes([]) == 0
+
+
+@pytest.mark.parametrize(
+    "change,squarings,needle",
+    [
+        ({"scheme": 1}, 0, "scheme 0"),
+        ({"eq_version": 0}, 0, "eq_version"),
+        ({"modified": 5}, 0, "modified"),
+        ({"dt": -1.0}, 0, "dt"),
+        ({}, 61, "squarings"),
+        ({}, -2, "squarings"),
+    ],
+)
+def test_stability_tool_rejects_bad_sets_on_the_host(change, squarings, needle):
+    """Rejected before any device work (the pointers are never touched)."""
+    from paper_1106_0785_amd import stability
+
+    lib = stability._lib()
+    p = dict(inputs.params(1, 1, 1e-3, 1e-3, 1e-5, [1e5] * 16, ["periodic"] * 4), **change)
+    ps, ss, n = stability._sets([p], [(1.0, 0.1, 0.0, 1.0)])
+    fake = ctypes.c_void_p(1 << 20)  # 256-aligned, never dereferenced
+    nbytes = stability.lbm_stability_workspace_bytes(1)
+    rc = lib.lbm_stability_radius(ps, ss, 1, fake, 4, squarings, fake, nbytes, fake, None)
+    assert rc == -1
+    assert needle in lbm.load().lbm_last_error().decode()
+    if not change:
+        return
+    rc = lib.lbm_stability_matrix(ps, ss, 1, fake, 4, fake, nbytes, fake, None)
+    assert rc == -1
+
+
+def test_stability_workspace_and_state_checks():
+    from paper_1106_0785_amd import stability
+
+    lib = stability._lib()
+    assert stability.lbm_stability_workspace_bytes(0) == 0
+    assert stability.lbm_stability_workspace_bytes(3) >= 3 * 5 * 256 * 8
+    p = inputs.params(1, 1, 1e-3, 1e-3, 1e-5, [1e5] * 16, ["periodic"] * 4)
+    fake = ctypes.c_void_p(1 << 20)
+    ps, ss, n = stability._sets([p], [(1.0, 0.1, 0.0, -1.0)])
+    assert lib.lbm_stability_radius(ps, ss, 1, fake, 4, 0, fake, 1 << 20, fake, None) == -1
+    assert "T > 0" in lbm.load().lbm_last_error().decode()
+    ps, ss, n = stability._sets([p], [(1.0, 0.1, 0.0, 1.0)])
+    assert lib.lbm_stability_radius(ps, ss, 1, fake, 4, 0, fake, 16, fake, None) == -2
