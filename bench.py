@@ -152,9 +152,10 @@ def bench_batch(steps, seed=0, n=512, plain=True, two_d=False):
 
 
 def bench_adjoint(nx=512, ny=128, steps=2000):
-    """Shock/interface problem at 512 x 128, 2000 steps: plain forward time
-    against the adjoint form's checkpointed forward and its backward sweep
-    (loss = half the squared misfit of the final density)."""
+    """Shock/interface problem (512 x 128 x 2000 steps by default; 4096 x
+    1024 x 36 steps for the HBM-resident figure): plain forward time against
+    the adjoint form's checkpointed forward and its backward sweep (loss =
+    half the squared misfit of the final density)."""
     import torch
 
     from paper_1106_0785_amd import inputs, lbm
@@ -308,7 +309,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--quick", action="store_true", help="headline workload only")
-    ap.add_argument("--only", choices=["batch", "batch2d", "adjoint", "limited", "stability"], help="run one side measurement alone and print "
+    ap.add_argument("--only", choices=["batch", "batch2d", "adjoint", "adjoint_hbm", "limited", "stability"], help="run one side measurement alone and print "
                     "its JSON (for profiling; not the benchmark line)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -330,6 +331,9 @@ def main():
         return
     if args.only == "adjoint":
         print(json.dumps(bench_adjoint()), flush=True)
+        return
+    if args.only == "adjoint_hbm":
+        print(json.dumps(bench_adjoint(4096, 1024, 36)), flush=True)
         return
     if args.only == "stability":
         print(json.dumps(bench_stability(reps=2, cpu_points=8)), flush=True)
@@ -366,6 +370,8 @@ def main():
         extra["batch_rm2d_96"] = bench_batch(200, n=96, two_d=True)
         log("adjoint rm 512x128, 2000 steps")
         extra["adjoint_rm_512x128"] = bench_adjoint()
+        log("adjoint rm 4096x1024, 36 steps (HBM-resident)")
+        extra["adjoint_rm_4096x1024"] = bench_adjoint(4096, 1024, 36)
         log("stability map: Fig. 2 cases, 512 x 512 wavenumbers")
         extra["stability_fig2_512x512"] = bench_stability()
 

@@ -21,7 +21,7 @@ struct AdjLayout {
   int C, K;               // checkpoint interval, segments
   long long pitch, plane;  // distribution layout
   int gx, gy;             // adjoint launch grid
-  size_t consts, adj, ckpt, seg, lam, rec, partials, flag, total;
+  size_t consts, adj, ckpt, seg, lam, rec, partials, red, red_bytes, flag, total;
 };
 
 lbm_status adj_layout(const lbm_params* p, int64_t nsteps, int32_t ckpt, AdjLayout* L) {
@@ -54,6 +54,10 @@ lbm_status adj_layout(const lbm_params* p, int64_t nsteps, int32_t ckpt, AdjLayo
   off += 2 * a256((size_t)NREC * L->plane * sizeof(double));
   L->partials = off;
   off += a256((size_t)L->gx * L->gy * 12 * sizeof(double));
+  // two ping-pong buffers for the chunked reduction of the partials
+  L->red = off;
+  L->red_bytes = a256((size_t)((L->gx * L->gy + ADJ_CHUNK - 1) / ADJ_CHUNK) * 12 * sizeof(double));
+  off += 2 * L->red_bytes;
   L->flag = off;
   off += 256;
   L->total = off;
@@ -82,6 +86,7 @@ struct lbm_adjoint {
     return (double*)(base + L.rec + (size_t)j * a256((size_t)NREC * L.plane * sizeof(double)));
   }
   double* partials() { return (double*)(base + L.partials); }
+  double* red(int j) { return (double*)(base + L.red + (size_t)j * L.red_bytes); }
   int* flag() { return (int*)(base + L.flag); }
   Field field(const double* fin, double* fout) {
     Field F;
@@ -211,7 +216,10 @@ lbm_status lbm_adjoint_backward(lbm_adjoint* a, const double* d_rho0, const doub
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "adjoint set-up launch");
   auto krec = ver == 2 ? k_adj_records<2> : ver == 3 ? k_adj_records<3> : k_adj_records<1>;
-  auto kstep = ver == 2 ? k_adj_step<2> : ver == 3 ? k_adj_step<3> : k_adj_step<1>;
+  // grids of more than 2048 blocks (8 per CU) take the two-blocks-per-CU form
+  const bool wide = (long long)L.gx * L.gy > 2048;
+  auto kstep = wide ? (ver == 2 ? k_adj_step<2, true> : ver == 3 ? k_adj_step<3, true> : k_adj_step<1, true>)
+                    : (ver == 2 ? k_adj_step<2, false> : ver == 3 ? k_adj_step<3, false> : k_adj_step<1, false>);
   for (int k = L.K - 1; k >= 0; --k) {
     const int64_t n0 = (int64_t)k * L.C, n1 = std::min<int64_t>(n0 + L.C, a->nsteps);
     // recompute f^{n0+1} .. f^{n1-1} into the segment store (f^{n0} is the checkpoint)
@@ -241,8 +249,22 @@ lbm_status lbm_adjoint_backward(lbm_adjoint* a, const double* d_rho0, const doub
   auto kinit = ver == 2 ? k_adj_init<2> : ver == 3 ? k_adj_init<3> : k_adj_init<1>;
   hipLaunchKernelGGL(kinit, grow, dim3(64), 0, a->stream, a->field(a->ckpt(0), nullptr), a->lam(cur), d_rho0, d_ux0,
                      d_uy0, d_T0, d_grad_rho0, d_grad_ux0, d_grad_uy0, d_grad_T0);
-  if (d_grad_s)
-    hipLaunchKernelGGL(k_adj_reduce<0>, dim3(1), dim3(64), 0, a->stream, a->partials(), L.gx * L.gy, d_grad_s);
+  if (d_grad_s) {
+    // fixed-order reduction of the per-block partials: chunks of ADJ_CHUNK
+    // rows, repeated until one row is left
+    const double* in = a->partials();
+    long long rows = (long long)L.gx * L.gy;
+    int j = 0;
+    do {
+      const long long nout = (rows + ADJ_CHUNK - 1) / ADJ_CHUNK;
+      hipLaunchKernelGGL(k_adj_reduce<0>, dim3((unsigned)((nout * 12 + 255) / 256)), dim3(256), 0, a->stream, in,
+                         (int)rows, a->red(j));
+      in = a->red(j);
+      j ^= 1;
+      rows = nout;
+    } while (rows > 1);
+    hipLaunchKernelGGL(k_adj_grad<0>, dim3(1), dim3(64), 0, a->stream, in, d_grad_s);
+  }
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "adjoint finish launch");
   return LBM_OK;

@@ -145,6 +145,32 @@ LBM_HD void lam_point(const Field& F, const Hot& c, const double* __restrict__ l
   }
 }
 
+// Where the transposed convection finds lambda at stencil point (x + ox,
+// y + oy): the stored node k and how plane i maps onto it (0: plane i;
+// 1: mirror in x; 3: mirror in y; 2: fixed-state ghost, value 0). Lets the
+// caller load one plane at a time.
+struct LamSrc {
+  long long k;
+  int mode;
+};
+
+LBM_HD LamSrc lam_src(const Field& F, const Hot& c, int x, int y, int ox, int oy) {
+  const Src sx = resolve(x + ox, F.nx, c.bc[0], c.bc[1], 0);
+  const Src sy = resolve(y + oy, F.ny, c.bc[2], c.bc[3], 2);
+  LamSrc r;
+  r.k = (long long)sy.idx * F.pitch + sx.idx;
+  r.mode = (sx.mode == 2 || sy.mode == 2) ? 2 : (sx.mode == 1 ? 1 : (sy.mode == 1 ? 3 : 0));
+  return r;
+}
+
+// Plane I of lambda at a stencil point (same values as lam_point).
+template <int I>
+LBM_HD double lam_plane(const Field& F, const double* __restrict__ lam, LamSrc s) {
+  const int pl = (s.mode == 1) ? MIRROR_X[I] : ((s.mode == 3) ? MIRROR_Y[I] : I);
+  const double v = lam[s.k + (long long)pl * F.plane];
+  return (s.mode == 2) ? 0.0 : v;
+}
+
 // Transposed Lax-Wendroff increment of velocity I along one axis; v is the
 // velocity component, (pm, mm) the weights as the forward step applies them
 // to (f(x+e) - f, f(x-e) - f), zl/zh true when the low/high neighbour is a
@@ -168,26 +194,52 @@ LBM_HD double conv_t_axis(int v, const double* lc, double lo, double hi, double 
 // contribution to dL/ds_5..16 (index k - 5) into sg.
 // With f_prev (the forward level of the next adjoint step, same layout as
 // F.fin) also writes that step's record of this node into rec_out.
-template <int VER>
+// Per-plane part of the transposed convection and identity for velocity I,
+// with the new lambda stored at once (so no neighbour plane set is kept).
+template <int I>
+struct AdjOut {
+  LBM_HD static void run(const Field& F, const Hot& c, const double* __restrict__ lam_in, double* __restrict__ lam_out,
+                         long long k0, LamSrc sxp, LamSrc sxm, LamSrc syp, LamSrc sym, bool zxl, bool zxh, bool zyl,
+                         bool zyh, double* out) {
+    const double l = lam_in[k0 + (long long)I * F.plane];
+    double v = out[I];
+    if (VX[I] != 0) v += conv_t_axis(VX[I], c.lx, lam_plane<I>(F, lam_in, sxm), lam_plane<I>(F, lam_in, sxp), l, zxl, zxh);
+    if (VY[I] != 0) v += conv_t_axis(VY[I], c.ly, lam_plane<I>(F, lam_in, sym), lam_plane<I>(F, lam_in, syp), l, zyl, zyh);
+    out[I] = l + v;
+    lam_out[k0 + (long long)I * F.plane] = out[I];
+    AdjOut<I + 1>::run(F, c, lam_in, lam_out, k0, sxp, sxm, syp, sym, zxl, zxh, zyl, zyh, out);
+  }
+};
+template <>
+struct AdjOut<16> {
+  LBM_HD static void run(const Field&, const Hot&, const double* __restrict__, double* __restrict__, long long, LamSrc,
+                         LamSrc, LamSrc, LamSrc, bool, bool, bool, bool, double*) {}
+};
+
+// New adjoint lambda^n at node (x, y) into lam_out; adds this node's
+// contribution to dL/ds_5..16 (index k - 5) into sg.
+// With f_prev (the forward level of the next adjoint step, same layout as
+// F.fin) also writes that step's record of this node into rec_out.
+// Ordered so that few values are live at once: the distributions are
+// dropped after their moments, dL/ds is formed as soon as mu is known, and
+// the transposed convection loads one plane of each neighbour at a time.
+template <int VER, bool SERIAL = false>
 LBM_HD void adj_node(const Field& F, const Hot& c, const Cold* __restrict__ cold, const AdjCoef* __restrict__ adj,
                      const double* __restrict__ lam_in, double* __restrict__ lam_out, const double* __restrict__ rec,
                      const double* __restrict__ f_prev, double* __restrict__ rec_out, int x, int y, double* sg) {
   const long long k0 = (long long)y * F.pitch + x;
-  double f[16], l[16];
-#pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    f[i] = F.fin[k0 + i * F.plane];
-    l[i] = lam_in[k0 + i * F.plane];
-  }
   // --- forward quantities at the node
   double m[16];
-  moments_from_f(f, m);
+  {
+    double f[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) f[i] = F.fin[k0 + i * F.plane];
+    moments_from_f(f, m);
+  }
   const double rho = m[0], ir = 1.0 / rho;
   const double ux = m[1] * ir, uy = m[2] * ir;
   const double T = m[3] * ir - 0.5 * (ux * ux + uy * uy);
   const double rT = rho * T;
-  double q[16];
-  equilibrium_moments<VER, double>(m[0], m[1], m[2], m[3], q);
   // --- neighbour records: velocities for A, B and dL/dA, dL/dB
   double GAxp, GBxp, uxxp, uyxp, GAxm, GBxm, uxxm, uyxm, GAyp, GByp, uxyp, uyyp, GAym, GBym, uxym, uyym;
   rec_point(F, c, cold, rec, x, y, +1, 0, GAxp, GBxp, uxxp, uyxp);
@@ -197,16 +249,32 @@ LBM_HD void adj_node(const Field& F, const Hot& c, const Cold* __restrict__ cold
   const double A = (uxxp - uxxm) * c.inv2dx - (uyyp - uyym) * c.inv2dy;
   const double B = (uyxp - uyxm) * c.inv2dx + (uxyp - uxym) * c.inv2dy;
   // --- collision adjoint
-  double mu[16], nu[16];
-  minvt_apply(l, mu);
+  double mu[16];
+  {
+    double l[16];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) nu[k] = 0.0;
+    for (int i = 0; i < 16; ++i) l[i] = lam_in[k0 + i * F.plane];
+    minvt_apply(l, mu);
+  }
+  // --- dL/ds: d col_k/d s_k = -dt (m_k - q_k), plus the modification's
+  // coefficients (their s-derivatives already carry the factor dt)
+  {
+    double q[16];
+    equilibrium_moments<VER, double>(m[0], m[1], m[2], m[3], q);
+#pragma unroll
+    for (int k = 4; k < 16; ++k) sg[k - 4] = mu[k] * adj->mdt * (m[k] - q[k]);
+    const double a7 = rT * ux * A, b7 = rT * uy * B, b8 = rT * ux * B, a8 = rT * uy * A;
+    sg[0] += mu[6] * adj->dcm[0] * a7 + mu[7] * adj->dcm[6] * a8;   // s5
+    sg[1] += mu[6] * adj->dcm[2] * b7 + mu[7] * adj->dcm[4] * b8;   // s6
+    sg[2] += mu[6] * (adj->dcm[1] * a7 + adj->dcm[3] * b7);          // s7
+    sg[3] += mu[7] * (adj->dcm[5] * b8 + adj->dcm[7] * a8);          // s8
+  }
+  double nu[16];
 #pragma unroll
   for (int k = 4; k < 16; ++k) nu[k] = c.cq[k - 4] * mu[k];
-  // conserved-moment adjoint: -J_q^T nu + mu7 dg7/dc + mu8 dg8/dc, by dual numbers
-  double gc[4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
+  // conserved-moment adjoint: -J_q^T nu + mu7 dg7/dc + mu8 dg8/dc, by dual
+  // numbers, one derivative direction a at a time
+  auto dual_dir = [&](int a) -> double {
     Dual cc[4];
 #pragma unroll
     for (int b = 0; b < 4; ++b) cc[b] = Dual(m[b], a == b ? 1.0 : 0.0);
@@ -221,41 +289,38 @@ LBM_HD void adj_node(const Field& F, const Hot& c, const Cold* __restrict__ cold
     const Dual rTd = cc[0] * Td;
     const Dual g7 = c.cmod[0] * rTd * vxd * A + c.cmod[1] * rTd * vyd * B;
     const Dual g8 = c.cmod[2] * rTd * vxd * B + c.cmod[3] * rTd * vyd * A;
-    gc[a] = s + mu[6] * g7.d + mu[7] * g8.d;
+    return s + mu[6] * g7.d + mu[7] * g8.d;
+  };
+  double gc[4] = {0.0, 0.0, 0.0, 0.0};
+  if constexpr (SERIAL) {
+    // not unrolled: interleaving the four evaluations would hold four times
+    // the registers (this form runs two blocks per CU)
+#pragma unroll 1
+    for (int a = 0; a < 4; ++a) {
+      const double g = dual_dir(a);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) gc[b] = (a == b) ? g : gc[b];
+    }
+  } else {
+#pragma unroll
+    for (int a = 0; a < 4; ++a) gc[a] = dual_dir(a);
   }
   // velocity adjoint from the neighbours' gradient terms, then du/dc
   const double gux = (GAxm - GAxp) * c.inv2dx + (GBym - GByp) * c.inv2dy;
   const double guy = (GBxm - GBxp) * c.inv2dx - (GAym - GAyp) * c.inv2dy;
-  {
-    double r0, jx0, jy0;
-    density_momentum(f, r0, jx0, jy0);
-    const double ir0 = 1.0 / r0;
-    const double vx0 = jx0 * ir0, vy0 = jy0 * ir0;
-    gc[0] += -(vx0 * gux + vy0 * guy) * ir0;
-    gc[1] += gux * ir0;
-    gc[2] += guy * ir0;
-  }
+  gc[0] += -(ux * gux + uy * guy) * ir;
+  gc[1] += gux * ir;
+  gc[2] += guy * ir;
 #pragma unroll
   for (int k = 0; k < 4; ++k) nu[k] = gc[k];
   double out[16];
   mt_apply(nu, out);
-  // --- transposed convection and identity
-  double lxp[16], lxm[16], lyp[16], lym[16];
-  lam_point(F, c, lam_in, x, y, +1, 0, lxp);
-  lam_point(F, c, lam_in, x, y, -1, 0, lxm);
-  lam_point(F, c, lam_in, x, y, 0, +1, lyp);
-  lam_point(F, c, lam_in, x, y, 0, -1, lym);
+  // --- transposed convection and identity, plane by plane
+  const LamSrc sxp = lam_src(F, c, x, y, +1, 0), sxm = lam_src(F, c, x, y, -1, 0);
+  const LamSrc syp = lam_src(F, c, x, y, 0, +1), sym = lam_src(F, c, x, y, 0, -1);
   const bool zxl = x == 0 && c.bc[0] == BC_ZERO_GRADIENT, zxh = x == F.nx - 1 && c.bc[1] == BC_ZERO_GRADIENT;
   const bool zyl = y == 0 && c.bc[2] == BC_ZERO_GRADIENT, zyh = y == F.ny - 1 && c.bc[3] == BC_ZERO_GRADIENT;
-#pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    double v = out[i];
-    if (VX[i] != 0) v += conv_t_axis(VX[i], c.lx, lxm[i], lxp[i], l[i], zxl, zxh);
-    if (VY[i] != 0) v += conv_t_axis(VY[i], c.ly, lym[i], lyp[i], l[i], zyl, zyh);
-    out[i] = l[i] + v;
-  }
-#pragma unroll
-  for (int i = 0; i < 16; ++i) lam_out[k0 + i * F.plane] = out[i];
+  AdjOut<0>::run(F, c, lam_in, lam_out, k0, sxp, sxm, syp, sym, zxl, zxh, zyl, zyh, out);
   if (f_prev) {
     double fp[16], r[NREC];
 #pragma unroll
@@ -264,15 +329,6 @@ LBM_HD void adj_node(const Field& F, const Hot& c, const Cold* __restrict__ cold
 #pragma unroll
     for (int j = 0; j < NREC; ++j) rec_out[k0 + j * F.plane] = r[j];
   }
-  // --- dL/ds: d col_k/d s_k = -dt (m_k - q_k), plus the modification's
-  // coefficients (their s-derivatives already carry the factor dt)
-#pragma unroll
-  for (int k = 4; k < 16; ++k) sg[k - 4] = mu[k] * adj->mdt * (m[k] - q[k]);
-  const double a7 = rT * ux * A, b7 = rT * uy * B, b8 = rT * ux * B, a8 = rT * uy * A;
-  sg[0] += mu[6] * adj->dcm[0] * a7 + mu[7] * adj->dcm[6] * a8;   // s5
-  sg[1] += mu[6] * adj->dcm[2] * b7 + mu[7] * adj->dcm[4] * b8;   // s6
-  sg[2] += mu[6] * (adj->dcm[1] * a7 + adj->dcm[3] * b7);          // s7
-  sg[3] += mu[7] * (adj->dcm[5] * b8 + adj->dcm[7] * a8);          // s8
 }
 
 // Value of lane l (uniform) of a wave.
@@ -290,9 +346,14 @@ __device__ __forceinline__ double wave_sum(double v) {
   return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
 }
 
-// Launched with 64 x 4 threads per block.
-template <int VER>
-__global__ __launch_bounds__(256) void k_adj_step(Field F, const double* __restrict__ lam_in,
+// Launched with 64 x 4 threads per block. WIDE (large grids): two blocks per
+// CU, so that each SIMD has two waves to hide the latency of ~100 loads per
+// node (version 3 excepted: its Maxwellian terms would spill), at the cost of
+// evaluating the four dual directions one after another; otherwise one block
+// per CU with the four interleaved (small grids give each SIMD one wave
+// anyway, and then instruction-level parallelism is what hides latency).
+template <int VER, bool WIDE>
+__global__ __launch_bounds__(256, (WIDE && VER != 3) ? 2 : 1) void k_adj_step(Field F, const double* __restrict__ lam_in,
                                                   double* __restrict__ lam_out, const double* __restrict__ rec,
                                                   const Hot* __restrict__ hot, const Cold* __restrict__ cold,
                                                   const AdjCoef* __restrict__ adj, double* __restrict__ partials,
@@ -306,7 +367,8 @@ __global__ __launch_bounds__(256) void k_adj_step(Field F, const double* __restr
   double sg[12];
 #pragma unroll
   for (int k = 0; k < 12; ++k) sg[k] = 0.0;
-  if (x < F.nx && y < F.ny) adj_node<VER>(F, hs, cold, adj, lam_in, lam_out, rec, f_prev, rec_out, x, y, sg);
+  if (x < F.nx && y < F.ny)
+    adj_node<VER, WIDE && VER != 3>(F, hs, cold, adj, lam_in, lam_out, rec, f_prev, rec_out, x, y, sg);
   // deterministic block reduction, one slot per block, accumulated over steps
 #pragma unroll
   for (int k = 0; k < 12; ++k) {
@@ -405,15 +467,27 @@ __global__ void k_adj_init(Field F, const double* __restrict__ lam, const double
   adj_init_node<VER>(F, lam, rho, ux, uy, T, g_rho, g_ux, g_uy, g_T, x, y);
 }
 
-// dL/ds_1..16 from the per-block partials (fixed summation order).
+// One pass of the fixed-order reduction of per-block partials [nrows][12]:
+// out row r = sum of input rows r*CHUNK .. r*CHUNK + CHUNK - 1 (in order).
+constexpr int ADJ_CHUNK = 64;
 template <int U>
-__global__ void k_adj_reduce(const double* __restrict__ partials, int nslots, double* __restrict__ grad_s) {
-  const int k = threadIdx.x;
-  if (k >= 16) return;
+__global__ void k_adj_reduce(const double* __restrict__ in, int nrows, double* __restrict__ out) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long nout = ((long long)nrows + ADJ_CHUNK - 1) / ADJ_CHUNK;
+  if (i >= nout * 12) return;
+  const long long r = i / 12;
+  const int comp = (int)(i % 12);
+  const long long b0 = r * ADJ_CHUNK, b1 = min(b0 + ADJ_CHUNK, (long long)nrows);
   double s = 0.0;
-  if (k >= 4)
-    for (int b = 0; b < nslots; ++b) s += partials[(long long)b * 12 + (k - 4)];
-  grad_s[k] = s;
+  for (long long b = b0; b < b1; ++b) s += in[b * 12 + comp];
+  out[i] = s;
+}
+
+// dL/ds_1..16 from the last reduction row (s_1..s_4 have no effect).
+template <int U>
+__global__ void k_adj_grad(const double* __restrict__ row, double* __restrict__ grad_s) {
+  const int k = threadIdx.x;
+  if (k < 16) grad_s[k] = (k >= 4) ? row[k - 4] : 0.0;
 }
 
 template <int U>

@@ -83,6 +83,27 @@ def test_adjoint_matches_complex_step(name):
     assert worst <= 1e-9
 
 
+def test_wide_grid_adjoint_matches_complex_step():
+    """A grid of more than 2048 adjoint blocks (2112 x 260) takes the
+    two-blocks-per-CU form of the adjoint step; same check as above."""
+    nx, ny = 2112, 260
+    p, fl = inputs.smooth_periodic(seed=17, nx=nx, ny=ny, amp=0.06)
+    p["bc"] = ["specular", "specular", "periodic", "periodic"]
+    p["s"][4], p["s"][5], p["s"][6], p["s"][7] = 700.0, 900.0, 1200.0, 1500.0
+    steps = 6
+    rng = np.random.default_rng(3)
+    w_rho = rng.standard_normal((ny, nx))
+    w_T = rng.standard_normal((ny, nx))
+    d_fields = [rng.standard_normal((ny, nx)) for _ in range(4)]
+    d_logs = rng.standard_normal(16)
+    got, gs = _adjoint_directional(p, fl, steps, w_rho, w_T, d_fields, d_logs, ckpt=2)
+    ref = _complex_step(p, fl, steps, w_rho, w_T, d_fields, d_logs)
+    rel = abs(got - ref) / abs(ref)
+    log("wide-grid adjoint vs complex step: rel diff %.2e" % rel)
+    assert rel <= 1e-9
+    assert np.all(gs[:4] == 0.0)
+
+
 def _rm_loss_setup(nx=512, ny=128, steps=2000):
     torch = _torch()
     p, fl, meta = inputs.rm(seed=0, nx=nx, ny=ny)
