@@ -298,8 +298,23 @@ def cpu_baseline(budget_s=15.0):
     t0 = time.perf_counter()
     oracle.run(p, f, n, nthreads=nt)
     t = time.perf_counter() - t0
+    # the same oracle on one thread, a shorter sample
+    t1 = time.perf_counter()
+    n1 = 0
+    while time.perf_counter() - t1 < budget_s / 4:
+        f = oracle.run(p, f, 1, nthreads=1)
+        n1 += 1
+    t1 = time.perf_counter() - t1
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": 1024 * 256 * n / t / 1e6, "unit": "MLUPS", "cores": nt, "kind": "oracle",
-            "sample": "1024x256 shock/interface problem, %d time steps after 3 warm-up steps (%.1f s)" % (n, t)}
+            "sample": "1024x256 shock/interface problem, %d time steps after 3 warm-up steps (%.1f s)" % (n, t),
+            "value_1_thread": 1024 * 256 * n1 / t1 / 1e6, "sample_1_thread": "%d time steps (%.1f s)" % (n1, t1),
+            "cpu_model": model, "logical_cpus": os.cpu_count()}
 
 
 def main():
