@@ -41,8 +41,9 @@
 // Parity status: the algorithm is pinned by the CPU tests (closed-form
 // equilibria, transport coefficients, thermal Couette profile, gamma = 2
 // Riemann solutions, conservation, symmetry). The free equilibrium moments
-// of versions 2 and 3 are "parity unpinned" beyond symmetry properties: the
-// paper states them without a worked value.
+// of version 3 are pinned against the sampled Maxwellian's moments in closed
+// form; those of version 2 only by their symmetry under reflection and
+// rotation ("parity unpinned" beyond that: the paper gives no worked value).
 //
 // Scalar type is a template parameter so the same code runs in complex
 // arithmetic for complex-step derivatives (every operation used is analytic).

@@ -78,3 +78,36 @@ def test_init_reproduces_fields():
         np.testing.assert_allclose(m["uy"], uy, atol=1e-13)
         np.testing.assert_allclose(m["T"], T, rtol=1e-12)
         np.testing.assert_allclose(m["p"], rho * T, rtol=1e-12)
+
+
+@pytest.mark.parametrize("state", STATES[:4] + [(0.8, 1.3, -0.7, 0.6)])
+def test_version3_free_moments_are_sampled_maxwellian_moments(state):
+    """Version 3 (Sec. II): f^eq_12, 15, 16 are the moments of f^max_i =
+    rho/(2 pi T) exp(-|v_i - u|^2 / (2T)) sampled at the 16 velocities,
+    computed here with the closed-form polynomials Re z^4, Re z^5, -Im z^5
+    (z = v_x + i v_y) instead of the oracle's table of M."""
+    rho, ux, uy, T = state
+    V, _, _ = oracle.matrices()
+    want = np.zeros(16)
+    for vx, vy in V:
+        fmax = rho / (2.0 * math.pi * T) * math.exp(-((vx - ux) ** 2 + (vy - uy) ** 2) / (2.0 * T))
+        z = complex(vx, vy)
+        want += fmax * np.array([0.0] * 11 + [(z ** 4).real, 0.0, 0.0, (z ** 5).real, -(z ** 5).imag])
+    got = oracle.feq_moments(3, rho, ux, uy, T)
+    scale = max(1e-300, rho / T)
+    for k in (11, 14, 15):
+        assert abs(got[k] - want[k]) <= 1e-13 * scale * 32 ** 2, (k + 1, got[k], want[k])
+
+
+@pytest.mark.parametrize("version", [2, 3])
+def test_free_moments_rotate_with_the_velocity(version):
+    """A quarter turn u -> (-u_y, u_x) maps z -> i z, so the free moments must
+    satisfy f^12(Ru) = f^12(u), f^15(Ru) = f^16(u), f^16(Ru) = -f^15(u): a
+    wrong sign or coefficient in one of the printed version-2 forms fails."""
+    for rho, ux, uy, T in [(1.3, 0.2, -0.1, 0.9), (0.6, -1.1, 0.7, 2.2), (2.0, 3.0, 1.0, 1.5)]:
+        q = oracle.feq_moments(version, rho, ux, uy, T)
+        r = oracle.feq_moments(version, rho, -uy, ux, T)
+        tol = 1e-12 * max(1.0, np.max(np.abs(q)))
+        assert abs(r[11] - q[11]) <= tol
+        assert abs(r[14] - q[15]) <= tol
+        assert abs(r[15] + q[14]) <= tol
