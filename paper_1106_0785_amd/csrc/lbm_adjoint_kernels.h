@@ -117,38 +117,11 @@ LBM_HD void rec_point(const Field& F, const Hot& c, const Cold* __restrict__ col
   }
 }
 
-// lambda at stencil point (x + ox, y + oy) for the transposed convection
-// (mirror ghosts permuted, fixed-state ghosts zero; a zero-gradient ghost
-// returns the node's own lambda and the caller swaps the weights).
-LBM_HD void lam_point(const Field& F, const Hot& c, const double* __restrict__ lam, int x, int y,
-                                          int ox, int oy, double* l) {
-  const Src sx = resolve(x + ox, F.nx, c.bc[0], c.bc[1], 0);
-  const Src sy = resolve(y + oy, F.ny, c.bc[2], c.bc[3], 2);
-  if (sx.mode == 2 || sy.mode == 2) {
-#pragma unroll
-    for (int i = 0; i < 16; ++i) l[i] = 0.0;
-    return;
-  }
-  const long long k = (long long)sy.idx * F.pitch + sx.idx;
-  double t[16];
-#pragma unroll
-  for (int i = 0; i < 16; ++i) t[i] = lam[k + i * F.plane];
-  if (sx.mode == 1) {
-#pragma unroll
-    for (int i = 0; i < 16; ++i) l[i] = t[MIRROR_X[i]];
-  } else if (sy.mode == 1) {
-#pragma unroll
-    for (int i = 0; i < 16; ++i) l[i] = t[MIRROR_Y[i]];
-  } else {
-#pragma unroll
-    for (int i = 0; i < 16; ++i) l[i] = t[i];
-  }
-}
-
 // Where the transposed convection finds lambda at stencil point (x + ox,
 // y + oy): the stored node k and how plane i maps onto it (0: plane i;
-// 1: mirror in x; 3: mirror in y; 2: fixed-state ghost, value 0). Lets the
-// caller load one plane at a time.
+// 1: mirror in x, mirrored plane; 3: mirror in y; 2: fixed-state ghost,
+// value 0; a zero-gradient ghost gives the node's own lambda and the caller
+// swaps the weights). Lets the caller load one plane at a time.
 struct LamSrc {
   long long k;
   int mode;
@@ -163,7 +136,7 @@ LBM_HD LamSrc lam_src(const Field& F, const Hot& c, int x, int y, int ox, int oy
   return r;
 }
 
-// Plane I of lambda at a stencil point (same values as lam_point).
+// Plane I of lambda at a stencil point described by lam_src.
 template <int I>
 LBM_HD double lam_plane(const Field& F, const double* __restrict__ lam, LamSrc s) {
   const int pl = (s.mode == 1) ? MIRROR_X[I] : ((s.mode == 3) ? MIRROR_Y[I] : I);
