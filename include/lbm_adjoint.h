@@ -10,8 +10,9 @@
  * the reverse sweep recomputes each segment from its checkpoint into a
  * segment store and runs the hand-written adjoint step backwards through it
  * (about sqrt(nsteps) states each). Supported boundaries: periodic,
- * zero-gradient, specular, fixed-state ghosts (not NEQ walls); equilibrium
- * versions 1-3; modified 0-2.
+ * zero-gradient, specular, fixed-state ghosts and non-equilibrium
+ * extrapolation walls (Sec. IV.A; their transpose is applied before each
+ * adjoint step); equilibrium versions 1-3; modified 0-2; scheme 0 only.
  */
 #ifndef LBM_ADJOINT_H_
 #define LBM_ADJOINT_H_
@@ -26,7 +27,7 @@ typedef struct lbm_adjoint lbm_adjoint;
 
 /* Device workspace for p, nsteps and a checkpoint interval (0 = round(sqrt(nsteps))):
  * checkpoints, segment store, two adjoint buffers, two per-node record buffers, the
- * s-gradient partials and constants; 0 if invalid (also for NEQ walls). */
+ * s-gradient partials and constants; 0 if invalid (lbm_create's rules, or scheme 1). */
 size_t lbm_adjoint_workspace_bytes(const lbm_params* p, int64_t nsteps, int32_t ckpt_interval);
 
 lbm_status lbm_adjoint_create(const lbm_params* p, int64_t nsteps, int32_t ckpt_interval, void* d_workspace,

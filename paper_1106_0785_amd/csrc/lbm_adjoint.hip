@@ -27,7 +27,6 @@ struct AdjLayout {
 lbm_status adj_layout(const lbm_params* p, int64_t nsteps, int32_t ckpt, AdjLayout* L) {
   lbm_status st = validate(p);
   if (st != LBM_OK) return st;
-  if (has_walls(p)) return fail(LBM_EINVAL, "the adjoint form does not support NEQ walls");
   if (p->scheme != 0) return fail(LBM_EINVAL, "the adjoint form supports scheme 0 (Lax-Wendroff) only");
   if (nsteps < 1) return fail(LBM_EINVAL, "nsteps must be >= 1");
   if (ckpt < 0) return fail(LBM_EINVAL, "checkpoint interval must be >= 0");
@@ -101,7 +100,7 @@ struct lbm_adjoint {
 };
 
 static hipError_t step_into(lbm_adjoint* a, const double* fin, double* fout) {
-  return launch_step(a->field(fin, fout), a->dhot(), a->dcold(), a->p.eq_version, false, 0, 0,
+  return launch_step(a->field(fin, fout), a->dhot(), a->dcold(), a->p.eq_version, has_walls(&a->p), 0, 0,
                      default_tile(a->p.nx, a->p.ny), a->flag(), a->stream);
 }
 
@@ -216,6 +215,8 @@ lbm_status lbm_adjoint_backward(lbm_adjoint* a, const double* d_rho0, const doub
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "adjoint set-up launch");
   auto krec = ver == 2 ? k_adj_records<2> : ver == 3 ? k_adj_records<3> : k_adj_records<1>;
+  auto kwall = ver == 2 ? k_adj_walls<2> : ver == 3 ? k_adj_walls<3> : k_adj_walls<1>;
+  const bool walls = has_walls(&a->p);
   // grids of more than 2048 blocks (8 per CU) take the two-blocks-per-CU form
   const bool wide = (long long)L.gx * L.gy > 2048;
   auto kstep = wide ? (ver == 2 ? k_adj_step<2, true> : ver == 3 ? k_adj_step<3, true> : k_adj_step<1, true>)
@@ -234,9 +235,19 @@ lbm_status lbm_adjoint_backward(lbm_adjoint* a, const double* d_rho0, const doub
     // n - 1 is not recomputed yet and a records pass runs first.
     for (int64_t n = n1 - 1; n >= n0; --n) {
       const double* fn = (n == n0) ? a->ckpt(k) : a->seg((int)(n - n0));
-      const double* fprev = (n - 1 < n0) ? nullptr : (n - 1 == n0) ? a->ckpt(k) : a->seg((int)(n - 1 - n0));
+      // with NEQ walls lambda^{n+1} first takes the walls' transpose, so the
+      // records of every step come from a separate pass after it
+      const double* fprev =
+          (walls || n - 1 < n0) ? nullptr : (n - 1 == n0) ? a->ckpt(k) : a->seg((int)(n - 1 - n0));
       Field F = a->field(fn, nullptr);
-      if (n == n1 - 1) hipLaunchKernelGGL(krec, gblk, bblk, 0, a->stream, F, a->lam(cur), a->rec(rc), a->dhot());
+      if (walls) {
+        const double* fnext = (n + 1 == n1) ? a->ckpt(k + 1) : a->seg((int)(n + 1 - n0));
+        const int along = (a->p.bc[2] == LBM_BC_NEQ_WALL || a->p.bc[3] == LBM_BC_NEQ_WALL) ? a->p.nx : a->p.ny;
+        hipLaunchKernelGGL(kwall, dim3((along + 63) / 64), dim3(64), 0, a->stream, a->field(fnext, nullptr),
+                           a->lam(cur), a->dhot(), a->dcold());
+      }
+      if (walls || n == n1 - 1)
+        hipLaunchKernelGGL(krec, gblk, bblk, 0, a->stream, F, a->lam(cur), a->rec(rc), a->dhot());
       hipLaunchKernelGGL(kstep, gblk, bblk, 0, a->stream, F, a->lam(cur), a->lam(cur ^ 1), a->rec(rc), a->dhot(),
                          a->dcold(), a->dadj(), a->partials(), fprev, a->rec(rc ^ 1));
       e = hipGetLastError();

@@ -359,6 +359,83 @@ __global__ __launch_bounds__(256, (WIDE && VER != 3) ? 2 : 1) void k_adj_step(Fi
 
 namespace lbm {
 
+// Transpose of a non-equilibrium extrapolation wall (Sec. IV.A): the step
+// writes f_w = f^eq(rho_n, u_w, T_w) + f_n - f^eq(rho_n, u_n, T_n) from the
+// fluid neighbour's new distributions f_n, so lambda_n += (d f_w / d f_n)^T
+// lambda_w. With mu = M^-T lambda_w (f^eq = M^-1 q): the fixed-state
+// equilibrium depends on f_n through rho only (d rho / d f_i = 1), the
+// neighbour's through (rho, j, e) = the first four moments (M^T of their
+// derivatives), both by dual numbers through the step's own equilibria.
+template <int VER>
+LBM_HD void wall_t_apply(const double* wall, const double* fn, const double* lw, double* ln) {
+  double mu[16], m[16];
+  minvt_apply(lw, mu);
+  moments_from_f(fn, m);
+  const double uwx = wall[1], uwy = wall[2], ew = wall[3] + 0.5 * (uwx * uwx + uwy * uwy);
+  double g1 = 0.0;
+  {
+    const Dual r(m[0], 1.0);
+    Dual q[16];
+    equilibrium_moments<VER, Dual>(r, r * uwx, r * uwy, r * ew, q);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) g1 += mu[k] * q[k].d;
+  }
+  double nu[16];
+#pragma unroll
+  for (int k = 4; k < 16; ++k) nu[k] = 0.0;
+#pragma unroll 1
+  for (int a = 0; a < 4; ++a) {
+    Dual cc[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) cc[b] = Dual(m[b], a == b ? 1.0 : 0.0);
+    Dual q[16];
+    equilibrium_moments<VER, Dual>(cc[0], cc[1], cc[2], cc[3], q);
+    double g = 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) g += mu[k] * q[k].d;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) nu[b] = (a == b) ? g : nu[b];
+  }
+  double t[16];
+  mt_apply(nu, t);
+#pragma unroll
+  for (int i = 0; i < 16; ++i) ln[i] += lw[i] + g1 - t[i];
+}
+
+// Wall transposes of one adjoint step, applied to lambda^{n+1} before the
+// step's transpose; F.fin = f^{n+1}. One thread per node along the walled
+// sides (walls on one axis only); the wall node's own lambda is then 0 (the
+// step overwrites it). With two walls 3 nodes apart both act on the same
+// fluid node, in turn, in the same thread.
+template <int VER>
+__global__ __launch_bounds__(64) void k_adj_walls(Field F, double* __restrict__ lam, const Hot* __restrict__ hot,
+                                                  const Cold* __restrict__ cold) {
+  const bool ywalls = hot->bc[2] == BC_NEQ_WALL || hot->bc[3] == BC_NEQ_WALL;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (ywalls ? F.nx : F.ny)) return;
+  const int across = ywalls ? F.ny : F.nx;
+  for (int side = 0; side < 2; ++side) {
+    const int sd = (ywalls ? 2 : 0) + side;
+    if (hot->bc[sd] != BC_NEQ_WALL) continue;
+    const int wpos = side == 0 ? 0 : across - 1, npos = side == 0 ? 1 : across - 2;
+    const long long kw = ywalls ? (long long)wpos * F.pitch + i : (long long)i * F.pitch + wpos;
+    const long long kn = ywalls ? (long long)npos * F.pitch + i : (long long)i * F.pitch + npos;
+    double lw[16], fn[16], ln[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      lw[j] = lam[kw + j * F.plane];
+      fn[j] = F.fin[kn + j * F.plane];
+      ln[j] = lam[kn + j * F.plane];
+    }
+    wall_t_apply<VER>(cold->wall[sd], fn, lw, ln);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      lam[kn + j * F.plane] = ln[j];
+      lam[kw + j * F.plane] = 0.0;
+    }
+  }
+}
+
 // lambda at the final level from dL/d(rho, u_x, u_y, T) of the final fields
 // (any gradient pointer may be NULL); the fields are rho = m1, u = (m2, m3)/m1,
 // T = m4/m1 - |u|^2/2 (R = 1).

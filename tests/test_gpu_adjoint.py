@@ -56,6 +56,8 @@ CASES = {
     "unmodified_periodic": (["periodic"] * 4, {"modified": 0}),
     "version2_periodic": (["periodic"] * 4, {"eq_version": 2}),
     "printed_sign": (["specular", "specular", "periodic", "periodic"], {"modified": 2}),
+    "neq_walls_y": (["periodic", "periodic", "neq_wall", "neq_wall"], {}),
+    "neq_walls_x_version3": (["neq_wall", "neq_wall", "specular", "specular"], {"eq_version": 3}),
 }
 
 
@@ -65,6 +67,9 @@ def test_adjoint_matches_complex_step(name):
     p, fl = inputs.smooth_periodic(seed=13, nx=23, ny=17, amp=0.06, **kw)
     p["bc"] = bc
     p["wall"][0] = [1.03, 0.02, 0.0, 1.01]
+    p["wall"][1] = [1.0, 0.0, 0.05, 1.04]
+    p["wall"][2] = [1.0, -0.03, 0.0, 0.97]
+    p["wall"][3] = [1.0, 0.06, 0.0, 1.02]
     p["s"][4], p["s"][5], p["s"][6], p["s"][7] = 700.0, 900.0, 1200.0, 1500.0
     steps = 40
     rng = np.random.default_rng(1)
@@ -81,6 +86,47 @@ def test_adjoint_matches_complex_step(name):
         assert np.all(gs[:4] == 0.0)
     log("adjoint vs complex step (%s): max rel diff %.2e" % (name, worst))
     assert worst <= 1e-9
+
+
+@pytest.mark.parametrize("ny", [3, 5])
+def test_adjoint_walls_three_and_five_nodes_apart(ny):
+    """Walls on both ends of a short column: with ny = 3 both walls take
+    their values from the same fluid node."""
+    p, fl = inputs.smooth_periodic(seed=5, nx=9, ny=ny, amp=0.04)
+    p["bc"] = ["periodic", "periodic", "neq_wall", "neq_wall"]
+    p["wall"][2] = [1.0, 0.01, 0.0, 1.0]
+    p["wall"][3] = [1.0, 0.08, 0.0, 1.03]
+    rng = np.random.default_rng(ny)
+    w = rng.standard_normal((ny, 9))
+    d_fields = [rng.standard_normal((ny, 9)) for _ in range(4)]
+    d_logs = rng.standard_normal(16)
+    got, gs = _adjoint_directional(p, fl, 30, w, np.zeros((ny, 9)), d_fields, d_logs, ckpt=4)
+    ref = _complex_step(p, fl, 30, w, np.zeros((ny, 9)), d_fields, d_logs)
+    rel = abs(got - ref) / abs(ref)
+    log("adjoint with walls %d nodes apart vs complex step: rel diff %.2e" % (ny, rel))
+    assert rel <= 1e-9
+
+
+def test_couette_prandtl_sensitivity():
+    """The thermal Couette configuration (4 x 64, NEQ walls, Pr = 1) run to
+    steady state (20000 steps): d/d log(s7 s8) of the mid-channel temperature
+    bump (the Pr-dependent viscous heating of Sec. IV.A) against the oracle's
+    complex-step derivative."""
+    p, fl, meta = inputs.couette(1.0)
+    steps = 20000
+    ny, nx = 64, 4
+    w = np.zeros((ny, nx))
+    w[ny // 2, :] = 1.0 / nx  # mean temperature of the middle row
+    d_logs = np.zeros(16)
+    d_logs[6] = d_logs[7] = 1.0  # Pr = s7 / s5 up by the same factor in s7 and s8
+    zeros = [np.zeros((ny, nx)) for _ in range(4)]
+    got, gs = _adjoint_directional(p, fl, steps, np.zeros((ny, nx)), w, zeros, d_logs)
+    ref = _complex_step(p, fl, steps, np.zeros((ny, nx)), w, zeros, d_logs)
+    rel = abs(got - ref) / abs(ref)
+    log("Couette dT_mid/dlog Pr: adjoint %.6e, complex step %.6e, rel %.2e" % (got, ref, rel))
+    assert rel <= 1e-9
+    # a larger Pr (less conduction against the same viscous heating) raises the bump
+    assert got > 0.0
 
 
 def test_wide_grid_adjoint_matches_complex_step():
