@@ -10,13 +10,13 @@
  * 16 * (its node count) entries of a concatenated distribution array
  * ([16][ny][nx] per instance, instances back to back).
  *
- * Execution: one-dimensional instances ("lines"; a periodic one only up to
- * 128 nodes) are cut into chunks; a workgroup owns one chunk plus a halo of
+ * Execution: one-dimensional Lax-Wendroff instances ("lines"; a periodic one
+ * only up to 128 nodes) are cut into chunks; a workgroup owns one chunk plus a halo of
  * h nodes, advances it h steps in LDS and writes the chunk back, so K steps
  * are ceil(K/h) launches over every chunk. The other instances ("tiled") are
  * cut into 64-column tiles of a common height and take one launch per step
- * and per (equilibrium version, wall variant) group, every tile of every
- * such instance in the same launch. One call of lbm_batch_step(b, K) is
+ * and per (equilibrium version, variant: plain, NEQ walls, flux-limited)
+ * group, every tile of every such instance in the same launch. One call of lbm_batch_step(b, K) is
  * captured once in a hipGraph and replayed on later calls with the same K.
  * Results equal those of lbm_step on each instance alone.
  */
@@ -33,8 +33,9 @@ typedef struct lbm_batch lbm_batch;
 
 /* Device workspace for n instances (two arenas, a backup arena used by the
  * tuner, descriptors, chunk and tile lists, budgets, status); 0 if n < 1 or
- * any instance is invalid (lbm_create's rules) or uses scheme 1 (the batched
- * form runs the Lax-Wendroff scheme only). */
+ * any instance is invalid (lbm_create's rules). Instances with the
+ * flux-limited scheme (scheme 1) are advanced tile by tile, whatever their
+ * shape. */
 size_t lbm_batch_workspace_bytes(const lbm_params* inst, int32_t n);
 
 /* Binds a batch to caller-owned workspace and stream (as lbm_create). */

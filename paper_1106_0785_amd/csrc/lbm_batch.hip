@@ -56,7 +56,7 @@ struct lbm_batch {
   int ntiles;      // tiles at the current tile height
   int max_tiles;   // room in tile_inst (tiles at the smallest height)
   int tile_rows;   // rows per tile of the tiled instances
-  int tbegin[4][2], tend[4][2];
+  int tbegin[4][3], tend[4][3];  // [version][variant: 0 plain, 1 NEQ walls, 2 flux-limited]
   int max_chunks;
   int* budget;
   int* flag;
@@ -75,9 +75,11 @@ static long long line_len(const lbm_params& p) { return (long long)p.nx * p.ny; 
 
 static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
-// A problem runs through the line kernel when it is one-dimensional and, if
-// periodic, fits one line region; otherwise tile by tile.
+// A problem runs through the line kernel when it is one-dimensional, uses the
+// Lax-Wendroff scheme and, if periodic, fits one line region; otherwise tile
+// by tile.
 static bool is_line(const lbm_params& p) {
+  if (p.scheme != 0) return false;
   if (p.nx != 1 && p.ny != 1) return false;
   const int axis = (p.ny == 1 && p.nx > 1) ? 0 : 1;
   return !(p.bc[2 * axis] == LBM_BC_PERIODIC && line_len(p) > 128);
@@ -95,6 +97,9 @@ static int batch_tile_rows(const lbm_params* inst, int32_t n) {
   }
   return rows;
 }
+
+// Tile-kernel variant of a tiled instance: 0 plain, 1 NEQ walls, 2 flux-limited.
+static int tile_variant(const lbm_params& p) { return p.scheme == 1 ? 2 : (has_walls(&p) ? 1 : 0); }
 
 struct Layout {
   size_t arena_bytes, insts_off, chunks_off, tinsts_off, tiles_off, budget_off, flag_off, backup_off, total;
@@ -117,8 +122,6 @@ static lbm_status layout_of(const lbm_params* inst, int32_t n, Layout* L) {
   for (int i = 0; i < n; ++i) {
     lbm_status st = LBM_OK;
     if (st != LBM_OK) return fail(st, "instance %d: %s", i, lbm_last_error());
-    if (inst[i].scheme != 0)
-      return fail(LBM_EINVAL, "instance %d: the batched form supports scheme 0 (Lax-Wendroff) only", i);
     const lbm_params& p = inst[i];
     if (is_line(p)) {
       const long long N = line_len(p);
@@ -192,11 +195,11 @@ static lbm_status build_tiles(lbm_batch* b, int rows) {
   std::vector<int> tiles;
   for (TileInst& T : b->host_tinsts) T.geom = march_geom(T.nx, T.ny, TileShape{rows, WAVES});
   for (int ver = 1; ver <= 3; ++ver)
-    for (int w = 0; w < 2; ++w) {
+    for (int w = 0; w < 3; ++w) {
       b->tbegin[ver][w] = (int)tiles.size();
       for (size_t j = 0; j < b->host_tinsts.size(); ++j) {
         const lbm_params& p = b->params[b->host_tinsts[j].gidx];
-        if (p.eq_version != ver || (int)has_walls(&p) != w) continue;
+        if (p.eq_version != ver || tile_variant(p) != w) continue;
         b->host_tinsts[j].first_tile = (int)tiles.size() - b->tbegin[ver][w];
         for (int t = 0; t < b->host_tinsts[j].geom.ntiles; ++t) tiles.push_back((int)j);
       }
@@ -255,15 +258,17 @@ static hipError_t enqueue_steps(lbm_batch* b, int64_t nsteps, int start_cur, int
   int cur2 = start_cur2;
   for (int64_t n = 0; (what & 2) && b->ntiles > 0 && n < nsteps; ++n) {
     for (int ver = 1; ver <= 3; ++ver)
-      for (int w = 0; w < 2; ++w) {
+      for (int w = 0; w < 3; ++w) {
         const int nt = b->tend[ver][w] - b->tbegin[ver][w];
         if (nt == 0) continue;
         const int per_xcd = (nt + 7) / 8;
-        decltype(&k_batch_tiles<1, false>) k;
-        if (w)
-          k = ver == 2 ? k_batch_tiles<2, true> : ver == 3 ? k_batch_tiles<3, true> : k_batch_tiles<1, true>;
+        decltype(&k_batch_tiles<1, false, 1>) k;
+        if (w == 1)
+          k = ver == 2 ? k_batch_tiles<2, true, 1> : ver == 3 ? k_batch_tiles<3, true, 1> : k_batch_tiles<1, true, 1>;
+        else if (w == 2)
+          k = ver == 2 ? k_batch_tiles<2, false, 2> : ver == 3 ? k_batch_tiles<3, false, 2> : k_batch_tiles<1, false, 2>;
         else
-          k = ver == 2 ? k_batch_tiles<2, false> : ver == 3 ? k_batch_tiles<3, false> : k_batch_tiles<1, false>;
+          k = ver == 2 ? k_batch_tiles<2, false, 1> : ver == 3 ? k_batch_tiles<3, false, 1> : k_batch_tiles<1, false, 1>;
         hipLaunchKernelGGL(k, dim3(8 * per_xcd), dim3(64 * WAVES), 0, stream, b->arena[cur2], b->arena[cur2 ^ 1],
                            b->tinsts, b->tile_inst + b->tbegin[ver][w], nt, per_xcd, b->budget, (int)n, (int)nsteps,
                            b->flag);

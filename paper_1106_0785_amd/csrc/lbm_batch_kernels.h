@@ -187,13 +187,14 @@ struct TileInst {
 };
 
 // One time step of every tile of a group of tile instances (same
-// equilibrium version and wall variant); workgroup b takes tile
+// equilibrium version and variant: NEQ walls, or the flux-limited scheme
+// with its radius-2 stencil HR = 2); workgroup b takes tile
 // (b mod 8) per_xcd + b / 8 of the group's list, so each XCD gets a
 // contiguous run. An instance whose budget b is spent (step n >= b of a call
 // of nsteps steps) idles: its final state stays where step b - 1 put it, and
 // at n == b it is copied across once if the remaining nsteps - b steps are
 // odd, so that after the call it sits in the same buffer as everyone else's.
-template <int VER, bool WALLS>
+template <int VER, bool WALLS, int HR>
 __global__ __launch_bounds__(64 * WAVES, 2) void k_batch_tiles(const double* __restrict__ A, double* __restrict__ B,
                                                                 const TileInst* __restrict__ insts,
                                                                 const int* __restrict__ tile_inst, int ntiles,
@@ -221,7 +222,7 @@ __global__ __launch_bounds__(64 * WAVES, 2) void k_batch_tiles(const double* __r
       for (int i = 0; i < 16; ++i) F.fout[i * F.plane + (long long)y * F.pitch + x] = F.fin[i * F.plane + (long long)y * F.pitch + x];
     return;
   }
-  fused_tile<VER, WALLS, WAVES, 1>(F, &I.hot, &I.cold, I.geom, tile, flag);
+  fused_tile<VER, WALLS, WAVES, HR>(F, &I.hot, &I.cold, I.geom, tile, flag);
 }
 
 }  // namespace lbm

@@ -225,3 +225,33 @@ def test_mixed_tile_heights_agree(rows):
     assert np.array_equal(f, ref)
     b.close()
     r.close()
+
+
+def test_batch_with_the_flux_limited_scheme():
+    """Instances with the flux-limited scheme (2-D set-ups and lines, which
+    then run tile by tile) beside Lax-Wendroff ones: bitwise equal to the
+    single-problem path, and within 1e-11 of the oracle."""
+    from paper_1106_0785_amd.batch import Batch
+
+    items = inputs.mixed_batch(seed=4, n=12)
+    for i, (kind, p, fl) in enumerate(items):
+        if "neq_wall" not in p["bc"] and (i % 2 == 1 or i == 0):
+            p["scheme"] = 1
+    assert sum(p.get("scheme", 0) for _, p, _ in items) >= 4
+    b = Batch([p for _, p, _ in items])
+    b.init([f for _, _, f in items])
+    b.step(61)
+    b.check()
+    fb = b.get_f().cpu().numpy()
+    m = {k: v.cpu().numpy() for k, v in b.moments().items()}
+    for i, (kind, p, fl) in enumerate(items):
+        _, gf = gpu_run(p, fl, 61)
+        fi = b.f_of(fb, i)
+        if p.get("scheme", 0) == 1 or (p["nx"] > 1 and p["ny"] > 1) or kind == "periodic_line":
+            assert np.array_equal(fi, gf), (i, kind, p.get("scheme", 0), _rel(fi, gf))
+        else:
+            assert _rel(fi, gf) <= 1e-12, (i, kind)
+        o, _ = oracle_run(p, fl, 61)
+        assert_parity({k: b.split(v, i) for k, v in m.items()}, o,
+                      what="batch instance %d (%s, scheme %d)" % (i, kind, p.get("scheme", 0)))
+    b.close()
