@@ -133,9 +133,13 @@ lbm_status lbm_set_f(lbm_handle* h, const double* d_f);
  * T <= 0 or a NaN; the flag is then cleared. */
 lbm_status lbm_check(lbm_handle* h);
 
-/* Kernel variant used by lbm_step: 0 = the fused LDS-staged kernel (default),
- * 1 = the plain one-thread-per-node global-memory kernel (a reference for
- * race and indexing checks). lbm_set_tile sets the tile shape of variant 0:
+/* Kernel variant used by lbm_step: 0 = the fused LDS-staged kernel (default
+ * for grids of more than 512 nodes), 1 = the plain one-thread-per-node
+ * global-memory kernel (a reference for race and indexing checks), 2 = the
+ * small-grid kernel (default when nx ny <= 512 and scheme 0; LBM_EINVAL
+ * otherwise): one workgroup holds the whole grid in LDS and takes up to 65536
+ * steps per launch, so such grids are not bound by launch cost.
+ * lbm_set_tile sets the tile shape of variant 0:
  * rows per workgroup tile (1..1024, rounded up to a multiple of waves) and
  * wavefronts per workgroup (2 or 4; problems with NEQ walls always use 4).
  * Results do not depend on the tile shape. */

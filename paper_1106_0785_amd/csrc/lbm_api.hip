@@ -163,6 +163,23 @@ hipError_t launch_step(const Field& F, const Hot* c, const Cold* cold, int versi
   return hipGetLastError();
 }
 
+// True when the whole grid fits the one-workgroup multi-step kernel.
+bool small_problem(const lbm_params* p) {
+  return p->scheme == 0 && (long long)p->nx * p->ny <= SMALL_NODES;
+}
+
+hipError_t launch_small(const Field& F, const Hot* c, const Cold* cold, int version, bool walls, int nsteps,
+                        int* flag, hipStream_t s) {
+  decltype(&k_step_small<1, false>) k;
+  if (walls)
+    k = version == 2 ? k_step_small<2, true> : version == 3 ? k_step_small<3, true> : k_step_small<1, true>;
+  else
+    k = version == 2 ? k_step_small<2, false> : version == 3 ? k_step_small<3, false> : k_step_small<1, false>;
+  const int threads = (F.nx * F.ny + 63) / 64 * 64;
+  hipLaunchKernelGGL(k, dim3(1), dim3(threads), 0, s, F, c, cold, nsteps, flag);
+  return hipGetLastError();
+}
+
 TileShape default_tile(int nx, int ny) {
   // tall tiles amortise the two halo rows; keep at least ~2 workgroups per CU
   const long long strips = (nx + STRIP - 1) / STRIP;
@@ -234,7 +251,7 @@ lbm_status lbm_create(const lbm_params* p, void* d_workspace, size_t ws_bytes, v
   h->flag = (int*)(base + 2 * 16 * h->plane * sizeof(double));
   h->dev = (Consts*)(base + 2 * 16 * h->plane * sizeof(double) + 256);
   h->cur = 0;
-  h->variant = 0;
+  h->variant = small_problem(p) ? 2 : 0;
   h->tile = default_tile(p->nx, p->ny);
   e = hipMemsetAsync(h->flag, 0, 256, h->stream);
   if (e == hipSuccess)
@@ -268,6 +285,18 @@ lbm_status lbm_init(lbm_handle* h, const double* d_rho, const double* d_ux, cons
 lbm_status lbm_step(lbm_handle* h, int64_t nsteps) {
   if (!h) return fail(LBM_EINVAL, "handle is NULL");
   if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
+  if (h->variant == 2) {
+    // whole grid in one workgroup: up to SMALL_CHUNK steps per launch
+    constexpr int64_t SMALL_CHUNK = 1 << 16;
+    for (int64_t n = 0; n < nsteps; n += SMALL_CHUNK) {
+      const int k = (int)std::min<int64_t>(SMALL_CHUNK, nsteps - n);
+      hipError_t e = launch_small(field_of(h, h->cur), &h->dev->hot, &h->dev->cold, h->p.eq_version,
+                                  has_walls(&h->p), k, h->flag, h->stream);
+      if (e != hipSuccess) return hip_fail(e, "small-problem kernel launch");
+      h->cur ^= 1;
+    }
+    return LBM_OK;
+  }
   for (int64_t n = 0; n < nsteps; ++n) {
     hipError_t e =
         launch_step(field_of(h, h->cur), &h->dev->hot, &h->dev->cold, h->p.eq_version, has_walls(&h->p),
@@ -323,7 +352,9 @@ lbm_status lbm_check(lbm_handle* h) {
 
 lbm_status lbm_set_variant(lbm_handle* h, int32_t variant) {
   if (!h) return fail(LBM_EINVAL, "handle is NULL");
-  if (variant != 0 && variant != 1) return fail(LBM_EINVAL, "variant must be 0 or 1");
+  if (variant < 0 || variant > 2) return fail(LBM_EINVAL, "variant must be 0, 1 or 2");
+  if (variant == 2 && !small_problem(&h->p))
+    return fail(LBM_EINVAL, "variant 2 needs scheme 0 and nx ny <= %d nodes", SMALL_NODES);
   h->variant = variant;
   return LBM_OK;
 }

@@ -201,6 +201,92 @@ __global__ __launch_bounds__(256) void k_step_plain(Field F, const Hot* __restri
 }
 
 // ---------------------------------------------------------------------------
+// Small problems (nx ny <= SMALL_NODES nodes): one workgroup holds the whole
+// grid in LDS (two buffers of 16 planes) and advances it nsteps time steps in
+// one launch, one thread per node, with the plain kernel's stencil, ghost
+// rules and arithmetic. Such grids are bound by the cost of a launch, which
+// this pays once for many steps.
+// ---------------------------------------------------------------------------
+constexpr int SMALL_NODES = 512;
+
+template <int VER, bool WALLS>
+__global__ __launch_bounds__(SMALL_NODES) void k_step_small(Field F, const Hot* __restrict__ hot,
+                                                           const Cold* __restrict__ cold, int nsteps, int* flag) {
+  __shared__ double buf[2][16][SMALL_NODES];
+  __shared__ Hot hs;
+  stage_hot(hot, &hs);
+  const Hot& c = hs;
+  const int N = F.nx * F.ny;
+  const int t = threadIdx.x;
+  const bool active = t < N;
+  const int x = active ? t % F.nx : 0, y = active ? t / F.nx : 0;
+  if (active) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) buf[0][i][t] = F.fin[i * F.plane + (long long)y * F.pitch + x];
+  }
+  __syncthreads();
+  const Src cx = resolve(x, F.nx, c.bc[0], c.bc[1], 0), cy = resolve(y, F.ny, c.bc[2], c.bc[3], 2);
+  const Src sxp = resolve(x + 1, F.nx, c.bc[0], c.bc[1], 0), sxm = resolve(x - 1, F.nx, c.bc[0], c.bc[1], 0);
+  const Src syp = resolve(y + 1, F.ny, c.bc[2], c.bc[3], 2), sym = resolve(y - 1, F.ny, c.bc[2], c.bc[3], 2);
+  // the stencil point (sx, sy) of buffer b with its ghost rule
+  auto point = [&](int b, const Src& sx, const Src& sy, double* f) {
+    const int k = sy.idx * F.nx + sx.idx;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) f[i] = buf[b][i][k];
+    fix_ghost(cold, sx, sy, f);
+  };
+  const bool wall = WALLS && active && is_wall_node(c, x, y, F.nx, F.ny);
+  // a wall node's fluid neighbour and side (walls on one axis only)
+  int wnb = 0, wside = 0;
+  if (WALLS && wall) {
+    if (c.bc[2] == BC_NEQ_WALL && y == 0) { wnb = 1 * F.nx + x; wside = 2; }
+    else if (c.bc[3] == BC_NEQ_WALL && y == F.ny - 1) { wnb = (F.ny - 2) * F.nx + x; wside = 3; }
+    else if (c.bc[0] == BC_NEQ_WALL && x == 0) { wnb = y * F.nx + 1; wside = 0; }
+    else { wnb = y * F.nx + F.nx - 2; wside = 1; }
+  }
+  bool ok = true;
+  int P = 0;
+  for (int s = 0; s < nsteps; ++s) {
+    const int Q = P ^ 1;
+    if (active && !wall) {
+      double f[16], fxp[16], fxm[16], fyp[16], fym[16];
+      point(P, cx, cy, f);
+      point(P, sxp, cy, fxp);
+      point(P, sxm, cy, fxm);
+      point(P, cx, syp, fyp);
+      point(P, cx, sym, fym);
+      NbrVel nv;
+      velocity_of(fxp, nv.ux_xp, nv.uy_xp);
+      velocity_of(fxm, nv.ux_xm, nv.uy_xm);
+      velocity_of(fyp, nv.ux_yp, nv.uy_yp);
+      velocity_of(fym, nv.ux_ym, nv.uy_ym);
+      double out[16];
+      ok &= node_update<VER>(c, f, fxp, fxm, fyp, fym, nv, out);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) buf[Q][i][t] = out[i];
+    }
+    __syncthreads();
+    if (WALLS) {
+      if (wall) {
+        double fn[16], fw[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) fn[i] = buf[Q][i][wnb];
+        neq_wall<VER>(cold->wall[wside], fn, fw);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) buf[Q][i][t] = fw[i];
+      }
+      __syncthreads();
+    }
+    P = Q;
+  }
+  if (active) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) F.fout[i * F.plane + (long long)y * F.pitch + x] = buf[P][i][t];
+  }
+  if (!ok) flag[0] = 1;
+}
+
+// ---------------------------------------------------------------------------
 // Fused kernel. A workgroup of W wavefronts (2 or 4) owns a tile of STRIP =
 // 64 columns (one per lane, 512-byte aligned rows) by `rows` rows and marches
 // up it W rows at a time. With a stencil of radius HR (1: Lax-Wendroff; 2:

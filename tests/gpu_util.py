@@ -24,14 +24,18 @@ def log(msg):
     sys.stdout.flush()
 
 
-def gpu_run(p, fields, steps, variant=0, rows=None, waves=4):
+def gpu_run(p, fields, steps, variant=None, rows=None, waves=None):
+    """Runs the HIP path. variant None keeps the library's default kernel,
+    except that a tile shape (rows, waves) selects the fused kernel."""
     from paper_1106_0785_amd import lbm
 
     sim = lbm.Simulation(p)
-    if variant:
+    if variant is None and (rows or waves):
+        variant = 0
+    if variant is not None:
         sim.set_variant(variant)
-    if rows or waves != 4:
-        sim.set_tile(rows or 16, waves)
+    if rows or waves:
+        sim.set_tile(rows or 16, waves or 4)
     sim.init(**fields)
     sim.step(steps)
     out = {k: v.cpu().numpy() for k, v in sim.moments().items()}

@@ -219,3 +219,74 @@ def test_shock_bubble_small(waves):
     g, _ = gpu_run(p, fl, 2000, waves=waves)
     o, _ = oracle_run(p, fl, 2000)
     assert_parity(g, o, what="shock-bubble 120x40")
+
+
+# Grids of at most 512 nodes run by default in the one-workgroup kernel that
+# keeps the grid in LDS and takes many steps per launch (variant 2).
+SMALL = {
+    "periodic_v1": (["periodic"] * 4, {}, (23, 19)),
+    "periodic_v2": (["periodic"] * 4, {"eq_version": 2}, (23, 19)),
+    "periodic_v3": (["periodic"] * 4, {"eq_version": 3}, (23, 19)),
+    "unmodified": (["periodic"] * 4, {"modified": 0}, (23, 19)),
+    "printed_q8_sign": (["periodic"] * 4, {"modified": 2}, (23, 19)),
+    "zero_gradient_x_specular_y": (["zero_gradient", "zero_gradient", "specular", "specular"], {}, (31, 16)),
+    "specular_x_periodic_y": (["specular", "specular", "periodic", "periodic"], {}, (16, 31)),
+    "dirichlet_x": (["dirichlet_eq", "zero_gradient", "periodic", "periodic"], {}, (66, 7)),
+    "line_512": (["periodic"] * 4, {}, (512, 1)),
+    "column_512": (["periodic"] * 4, {}, (1, 512)),
+    "one_node": (["periodic"] * 4, {}, (1, 1)),
+    "ragged_wave": (["periodic"] * 4, {}, (5, 13)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(SMALL))
+def test_small_grid_kernel(name):
+    bc, kw, (nx, ny) = SMALL[name]
+    p, fl = _small(9, nx, ny, bc, **kw)
+    if bc[0] == "dirichlet_eq":
+        p["wall"][0] = [1.05, 0.02, 0.0, 1.02]
+    log("small-grid kernel %s %dx%d 500 steps" % (name, nx, ny))
+    g, f2 = gpu_run(p, fl, 500, variant=2)
+    o, _ = oracle_run(p, fl, 500)
+    assert_parity(g, o, what="small-grid " + name)
+    _, f0 = gpu_run(p, fl, 500, variant=0)
+    d = _kernel_diff(f2, f0)
+    log("small-grid vs fused kernel: max diff %.2e" % d)
+    assert d <= 1e-13
+
+
+@pytest.mark.parametrize("axis", ["y", "x"])
+def test_small_grid_kernel_walls(axis):
+    """NEQ walls in the small-grid kernel, on either axis, with a step count
+    above one launch's chunk (65536) so the hand-over between launches is
+    exercised."""
+    if axis == "y":
+        p, fl, _ = inputs.couette(0.7, nx=4, ny=64)
+    else:
+        p, fl, _ = inputs.couette_x(2.0, nx=40, ny=3)
+    steps = 70000
+    log("small-grid kernel, NEQ walls on %s, %dx%d, %d steps" % (axis, p["nx"], p["ny"], steps))
+    g, f2 = gpu_run(p, fl, steps, variant=2)
+    _, f0 = gpu_run(p, fl, steps, variant=0)
+    d = _kernel_diff(f2, f0)
+    log("small-grid vs fused kernel after %d steps: max diff %.2e" % (steps, d))
+    assert d <= 1e-11
+    o, _ = oracle_run(p, fl, 3000)
+    g3, _ = gpu_run(p, fl, 3000, variant=2)
+    assert_parity(g3, o, what="small-grid walls on " + axis)
+
+
+def test_small_grid_variant_is_rejected_for_larger_grids():
+    from paper_1106_0785_amd import lbm
+
+    p, fl = _small(9, 33, 16, ["periodic"] * 4)  # 528 nodes
+    sim = lbm.Simulation(p)
+    with pytest.raises(lbm.LbmError):
+        sim.set_variant(2)
+    p, fl = _small(9, 32, 16, ["periodic"] * 4)
+    p["scheme"] = 1
+    sim2 = lbm.Simulation(p)
+    with pytest.raises(lbm.LbmError):
+        sim2.set_variant(2)
+    sim.close()
+    sim2.close()
