@@ -290,3 +290,14 @@ def test_small_grid_variant_is_rejected_for_larger_grids():
         sim2.set_variant(2)
     sim.close()
     sim2.close()
+
+
+@pytest.mark.parametrize("version", [1, 2, 3])
+def test_equal_rates_single_relaxation(version):
+    """Every rate equal (the single-relaxation limit of the three versions)."""
+    p, fl = _small(12, 70, 23, ["periodic"] * 4, eq_version=version)
+    p["s"] = [2.0e3] * 16
+    log("equal rates, version %d, 70x23 300 steps" % version)
+    g, _ = gpu_run(p, fl, 300)
+    o, _ = oracle_run(p, fl, 300)
+    assert_parity(g, o, what="equal rates v%d" % version)

@@ -103,3 +103,29 @@ def test_printed_q8_sign_breaks_isotropy():
     q = dict(p, nx=p["ny"], ny=p["nx"])
     b = oracle.run(q, _rotate(f0, v), 150)
     assert np.abs(_rotate(a, v) - b).max() > 1e-9
+
+
+def test_equal_rates_reduce_to_single_relaxation():
+    """Sec. II, the remark after the three equilibrium versions: with every
+    rate equal (S = s I) the model is a single-relaxation (BGK) model. Then
+    M^-1 S M = s I and the four modification terms vanish, so one step is
+    the pure convection of f minus dt s (f - f^eq(f)), with f^eq = M^-1 f^eq^
+    of f's own density, velocity and temperature. The convection-only step is
+    the oracle with every rate zero and the unmodified model; f^eq comes from
+    the oracle's initialiser. A wrong column of M^-1, a relaxed conserved
+    moment, a sign or a misplaced dt fails it."""
+    for version in (1, 2, 3):
+        p, fl = inputs.smooth_periodic(seed=31 + version, nx=11, ny=9, amp=0.08, eq_version=version)
+        f0 = oracle.run(p, oracle.init(p, **fl), 3)  # away from equilibrium
+        s = 3.7e3
+        conv = dict(p, s=[0.0] * 16, modified=0)
+        c = oracle.run(conv, f0, 1)
+        m = oracle.moments(p, f0)
+        feq = oracle.init(p, m["rho"], m["ux"], m["uy"], m["T"])
+        expect = c - p["dt"] * s * (f0 - feq)
+        assert np.max(np.abs(f0 - feq)) > 1e-4 * np.max(np.abs(f0))  # the relaxation term is not trivial
+        for modified in (0, 1, 2):
+            srt = dict(p, s=[s] * 16, modified=modified)
+            got = oracle.run(srt, f0, 1)
+            err = np.max(np.abs(got - expect)) / np.max(np.abs(f0))
+            assert err < 1e-13, (version, modified, err)
