@@ -5,6 +5,7 @@ paper-shaped workloads, plus edge cases. Tolerance: 1e-11 per moment field
 import numpy as np
 import pytest
 
+import oracle
 from gpu_util import assert_parity, gpu_run, log, oracle_run
 from paper_1106_0785_amd import inputs
 
@@ -301,3 +302,37 @@ def test_equal_rates_single_relaxation(version):
     g, _ = gpu_run(p, fl, 300)
     o, _ = oracle_run(p, fl, 300)
     assert_parity(g, o, what="equal rates v%d" % version)
+
+
+@pytest.mark.parametrize("bc", [["periodic"] * 4, ["specular", "zero_gradient", "periodic", "periodic"],
+                                ["dirichlet_eq", "specular", "zero_gradient", "specular"]])
+def test_state_changes_between_steps(bc):
+    """Everything that writes the distributions between steps (init,
+    restore from a checkpoint, a step of another kernel variant, the tuner's
+    probes and restore) leaves the next step a consistent state. Three
+    strips (nx = 150), several x boundary kinds."""
+    from paper_1106_0785_amd import lbm
+
+    p, fl = _small(13, 150, 21, bc)
+    if bc[0] == "dirichlet_eq":
+        p["wall"][0] = [1.04, 0.03, 0.0, 1.01]
+    f0 = oracle.init(p, **fl)
+    f20 = oracle.run(p, f0, 20)
+    sim = lbm.Simulation(p)
+    sim.init(**fl)
+    sim.step(7)
+    sim.set_f(f20)  # restore: the next step must not use the edges of step 7
+    sim.step(5)
+    sim.set_variant(1)
+    sim.step(4)  # plain kernel: leaves the edge copies stale
+    sim.set_variant(0)
+    sim.step(6)
+    sim.tune(probe_steps=2)  # probes, then restores the state
+    sim.step(5)
+    got = sim.get_f().cpu().numpy()
+    sim.check()
+    sim.close()
+    ref = oracle.run(p, f20, 20)
+    err = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+    log("state changes between steps, bc %s: max rel diff %.2e" % (bc, err))
+    assert err <= 1e-12
