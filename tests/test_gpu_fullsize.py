@@ -101,3 +101,42 @@ def test_adjoint_512x128_2000_steps_against_complex_step():
     # 9e-13 apart after 2000 steps); the bound leaves room for the growth of
     # rounding differences along the shocked trajectory
     assert rel <= 1e-10
+
+
+def test_grid_beyond_32_bit_offsets():
+    """A periodic 64 x 40 field tiled 257 x 410 times (16448 x 16400 nodes,
+    16 planes = 4.3e9 doubles per buffer, past 2^32 elements; 69 GB of
+    distributions): by translation invariance every node after 3 steps
+    equals the node of the 64 x 40 problem run alone, which matches the
+    oracle."""
+    import torch
+
+    from paper_1106_0785_amd import lbm
+
+    p, fl = inputs.smooth_periodic(seed=17, nx=64, ny=40, amp=0.07)
+    steps = 3
+    small = lbm.Simulation(p)
+    small.init(**fl)
+    small.step(steps)
+    gs = {k: v.cpu().numpy() for k, v in small.moments().items()}
+    small.check()
+    small.close()
+    o, _ = oracle_run(p, fl, steps)
+    assert_parity(gs, o, what="64x40 tile")
+
+    rx, ry = 257, 410
+    big = dict(p, nx=64 * rx, ny=40 * ry)
+    log("16448 x 16400 tiled periodic grid: %d steps" % steps)
+    sim = lbm.Simulation(big)
+    sim.init(**{k: torch.from_numpy(np.tile(v, (ry, rx))) for k, v in fl.items()})
+    sim.step(steps)
+    m = sim.moments()
+    sim.check()
+    for k in ("rho", "ux", "uy", "T", "p"):
+        got = m[k].cpu().numpy().reshape(ry, 40, rx, 64)
+        same = bool(np.array_equal(got, np.broadcast_to(gs[k][None, :, None, :], got.shape)))
+        log("  %s: every node equals its tile node: %s" % (k, same))
+        assert same, k
+    del m
+    sim.close()
+    torch.cuda.empty_cache()
