@@ -36,7 +36,7 @@ def test_batch_matches_single_problem_path_and_oracle():
     fb = b.get_f().cpu().numpy()
     worst = 0.0
     for i, (kind, p, fl) in enumerate(items):
-        g, gf = gpu_run(p, fl, steps)
+        g, gf = gpu_run(p, fl, steps, variant=0)
         d = float(np.max(np.abs(b.f_of(fb, i) - gf) / np.abs(gf).max(axis=(1, 2), keepdims=True)))
         worst = max(worst, d)
         assert d <= 1e-12, (i, kind, d)
@@ -71,7 +71,7 @@ def test_budgets():
     m = {k: v.cpu().numpy() for k, v in b.moments().items()}
     for i, (kind, p, fl) in enumerate(items):
         n = min(200, budgets[i])
-        _, gf = gpu_run(p, fl, n)
+        _, gf = gpu_run(p, fl, n, variant=0)
         d = float(np.max(np.abs(b.f_of(fb, i) - gf) / np.abs(gf).max(axis=(1, 2), keepdims=True)))
         assert d <= 1e-12, (i, budgets[i], d)
         o, _ = oracle_run(p, fl, n)
@@ -142,7 +142,7 @@ def test_mixed_batch_matches_single_problem_path_and_oracle():
     fb = b.get_f().cpu().numpy()
     kinds = set()
     for i, (kind, p, fl) in enumerate(items):
-        _, gf = gpu_run(p, fl, steps)
+        _, gf = gpu_run(p, fl, steps, variant=0)
         fi = b.f_of(fb, i)
         if p["nx"] > 1 and p["ny"] > 1 or kind == "periodic_line":
             assert np.array_equal(fi, gf), (i, kind, _rel(fi, gf))
@@ -164,7 +164,7 @@ def test_mixed_batch_budgets():
     m = {k: v.cpu().numpy() for k, v in b.moments().items()}
     for i, (kind, p, fl) in enumerate(items):
         n = min(101, budgets[i])
-        _, gf = gpu_run(p, fl, n)
+        _, gf = gpu_run(p, fl, n, variant=0)
         assert _rel(b.f_of(fb, i), gf) <= 1e-12, (i, kind, budgets[i])
         o, _ = oracle_run(p, fl, n)
         assert_parity({k: b.split(v, i) for k, v in m.items()}, o, what="budget %d mixed instance %d" % (n, i))
@@ -245,7 +245,7 @@ def test_batch_with_the_flux_limited_scheme():
     fb = b.get_f().cpu().numpy()
     m = {k: v.cpu().numpy() for k, v in b.moments().items()}
     for i, (kind, p, fl) in enumerate(items):
-        _, gf = gpu_run(p, fl, 61)
+        _, gf = gpu_run(p, fl, 61, variant=0)
         fi = b.f_of(fb, i)
         if p.get("scheme", 0) == 1 or (p["nx"] > 1 and p["ny"] > 1) or kind == "periodic_line":
             assert np.array_equal(fi, gf), (i, kind, p.get("scheme", 0), _rel(fi, gf))
