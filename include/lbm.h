@@ -75,7 +75,7 @@ enum { LBM_SIDE_XLO = 0, LBM_SIDE_XHI = 1, LBM_SIDE_YLO = 2, LBM_SIDE_YHI = 3 };
  *               zero-gradient layer repeats the boundary node, the second
  *               mirror layer mirrors the node next to it). Scheme 1 takes
  *               sharp discontinuities without smoothing; it is not available
- *               with NEQ walls, in the batched form or in the adjoint form. */
+ *               with NEQ walls or in the adjoint form. */
 typedef struct {
   int32_t nx, ny;
   double dx, dy, dt;

@@ -18,7 +18,9 @@
  * and per (equilibrium version, variant: plain, NEQ walls, flux-limited)
  * group, every tile of every such instance in the same launch. One call of lbm_batch_step(b, K) is
  * captured once in a hipGraph and replayed on later calls with the same K.
- * Results equal those of lbm_step on each instance alone.
+ * Results equal those of lbm_step with the fused kernel (variant 0) on each
+ * instance alone: bitwise for tiled instances, within rounding (the same
+ * arithmetic, multiply-adds contracted differently) for lines.
  */
 #ifndef LBM_BATCH_H_
 #define LBM_BATCH_H_
