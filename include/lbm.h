@@ -133,12 +133,20 @@ lbm_status lbm_set_f(lbm_handle* h, const double* d_f);
  * T <= 0 or a NaN; the flag is then cleared. */
 lbm_status lbm_check(lbm_handle* h);
 
-/* Kernel variant used by lbm_step: 0 = the fused LDS-staged kernel (default
- * for grids of more than 512 nodes), 1 = the plain one-thread-per-node
- * global-memory kernel (a reference for race and indexing checks), 2 = the
- * small-grid kernel (default when nx ny <= 512 and scheme 0; LBM_EINVAL
- * otherwise): one workgroup holds the whole grid in LDS and takes up to 65536
- * steps per launch, so such grids are not bound by launch cost.
+/* Kernel variant used by lbm_step:
+ *   0 the fused LDS-staged kernel, one launch per step (default for grids of
+ *     more than 512 nodes and more than 16 rows, and for scheme 1);
+ *   1 the plain one-thread-per-node global-memory kernel (a reference for
+ *     race and indexing checks);
+ *   2 the small-grid kernel (default when nx ny <= 512 and scheme 0;
+ *     LBM_EINVAL otherwise): one workgroup holds the whole grid in LDS and
+ *     takes up to 65536 steps per launch;
+ *   3 the narrow-grid kernel (default when ny <= 16, nx ny > 512 and scheme
+ *     0; LBM_EINVAL otherwise): workgroups hold overlapping windows of 64
+ *     columns (32 when ny > 8) by all rows in LDS and take up to 8 (4) steps
+ *     per launch, recomputing the overlap.
+ * Variants 2 and 3 take many steps per launch, so small and narrow grids are
+ * not bound by launch cost. All variants give the same results to rounding.
  * lbm_set_tile sets the tile shape of variant 0:
  * rows per workgroup tile (1..1024, rounded up to a multiple of waves) and
  * wavefronts per workgroup (2 or 4; problems with NEQ walls always use 4).

@@ -180,6 +180,36 @@ hipError_t launch_small(const Field& F, const Hot* c, const Cold* cold, int vers
   return hipGetLastError();
 }
 
+// True when the grid takes the narrow-grid (band) kernel: scheme 0, too big
+// for the small-grid kernel, at most 16 rows.
+bool band_problem(const lbm_params* p) {
+  return p->scheme == 0 && !small_problem(p) && p->ny <= 16;
+}
+
+// Window shape of the band kernel: 64 columns by ny <= 8 rows or 32 by ny
+// <= 16, h = wc / 8 steps per launch, the middle 3/4 of the columns written.
+BandGeom band_geom(int nx, int ny) {
+  BandGeom g;
+  g.wc = ny <= 8 ? 64 : 32;
+  g.h = g.wc / 8;
+  g.v = g.wc - 2 * g.h;
+  g.nwin = (nx + g.v - 1) / g.v;
+  return g;
+}
+
+hipError_t launch_band(const Field& F, const Hot* c, const Cold* cold, int version, bool walls, int nsteps,
+                       int* flag, hipStream_t s) {
+  const BandGeom g = band_geom(F.nx, F.ny);
+  decltype(&k_step_band<1, false>) k;
+  if (walls)
+    k = version == 2 ? k_step_band<2, true> : version == 3 ? k_step_band<3, true> : k_step_band<1, true>;
+  else
+    k = version == 2 ? k_step_band<2, false> : version == 3 ? k_step_band<3, false> : k_step_band<1, false>;
+  const int threads = (g.wc * F.ny + 63) / 64 * 64;
+  hipLaunchKernelGGL(k, dim3(g.nwin), dim3(threads), 0, s, F, c, cold, g, nsteps, flag);
+  return hipGetLastError();
+}
+
 TileShape default_tile(int nx, int ny) {
   // tall tiles amortise the two halo rows; keep at least ~2 workgroups per CU
   const long long strips = (nx + STRIP - 1) / STRIP;
@@ -251,7 +281,7 @@ lbm_status lbm_create(const lbm_params* p, void* d_workspace, size_t ws_bytes, v
   h->flag = (int*)(base + 2 * 16 * h->plane * sizeof(double));
   h->dev = (Consts*)(base + 2 * 16 * h->plane * sizeof(double) + 256);
   h->cur = 0;
-  h->variant = small_problem(p) ? 2 : 0;
+  h->variant = small_problem(p) ? 2 : band_problem(p) ? 3 : 0;
   h->tile = default_tile(p->nx, p->ny);
   e = hipMemsetAsync(h->flag, 0, 256, h->stream);
   if (e == hipSuccess)
@@ -293,6 +323,18 @@ lbm_status lbm_step(lbm_handle* h, int64_t nsteps) {
       hipError_t e = launch_small(field_of(h, h->cur), &h->dev->hot, &h->dev->cold, h->p.eq_version,
                                   has_walls(&h->p), k, h->flag, h->stream);
       if (e != hipSuccess) return hip_fail(e, "small-problem kernel launch");
+      h->cur ^= 1;
+    }
+    return LBM_OK;
+  }
+  if (h->variant == 3) {
+    // narrow grid: up to h steps per launch in LDS windows
+    const int64_t hmax = band_geom(h->p.nx, h->p.ny).h;
+    for (int64_t n = 0; n < nsteps; n += hmax) {
+      const int k = (int)std::min<int64_t>(hmax, nsteps - n);
+      hipError_t e = launch_band(field_of(h, h->cur), &h->dev->hot, &h->dev->cold, h->p.eq_version,
+                                 has_walls(&h->p), k, h->flag, h->stream);
+      if (e != hipSuccess) return hip_fail(e, "band kernel launch");
       h->cur ^= 1;
     }
     return LBM_OK;
@@ -352,9 +394,11 @@ lbm_status lbm_check(lbm_handle* h) {
 
 lbm_status lbm_set_variant(lbm_handle* h, int32_t variant) {
   if (!h) return fail(LBM_EINVAL, "handle is NULL");
-  if (variant < 0 || variant > 2) return fail(LBM_EINVAL, "variant must be 0, 1 or 2");
+  if (variant < 0 || variant > 3) return fail(LBM_EINVAL, "variant must be 0, 1, 2 or 3");
   if (variant == 2 && !small_problem(&h->p))
     return fail(LBM_EINVAL, "variant 2 needs scheme 0 and nx ny <= %d nodes", SMALL_NODES);
+  if (variant == 3 && !band_problem(&h->p))
+    return fail(LBM_EINVAL, "variant 3 needs scheme 0, ny <= 16 and nx ny > %d nodes", SMALL_NODES);
   h->variant = variant;
   return LBM_OK;
 }

@@ -336,3 +336,66 @@ def test_state_changes_between_steps(bc):
     err = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
     log("state changes between steps, bc %s: max rel diff %.2e" % (bc, err))
     assert err <= 1e-12
+
+
+# Narrow grids (at most 16 rows, more than 512 nodes) can run in the band
+# kernel (variant 3): LDS windows of all rows, several steps per launch.
+BAND = {
+    "periodic_2000x4": (["periodic"] * 4, {}, (2000, 4)),
+    "line_700": (["periodic"] * 4, {}, (700, 1)),
+    "specular_x_333x16": (["specular", "specular", "periodic", "periodic"], {}, (333, 16)),
+    "zero_gradient_x_specular_y_130x9": (["zero_gradient", "zero_gradient", "specular", "specular"], {}, (130, 9)),
+    "dirichlet_x_200x5": (["dirichlet_eq", "zero_gradient", "periodic", "periodic"], {}, (200, 5)),
+    "periodic_40x13_v2": (["periodic"] * 4, {"eq_version": 2}, (40, 13)),
+    "periodic_97x8_v3": (["periodic"] * 4, {"eq_version": 3}, (97, 8)),
+    "unmodified_515x1": (["periodic"] * 4, {"modified": 0}, (515, 1)),
+    "printed_q8_sign_90x7": (["periodic"] * 4, {"modified": 2}, (90, 7)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(BAND))
+def test_band_kernel(name):
+    bc, kw, (nx, ny) = BAND[name]
+    p, fl = _small(14, nx, ny, bc, **kw)
+    if bc[0] == "dirichlet_eq":
+        p["wall"][0] = [1.05, 0.02, 0.0, 1.02]
+    steps = 203  # not a multiple of the steps per launch
+    log("band kernel %s %dx%d %d steps" % (name, nx, ny, steps))
+    g, f3 = gpu_run(p, fl, steps, variant=3)
+    o, _ = oracle_run(p, fl, steps)
+    assert_parity(g, o, what="band " + name)
+    _, f0 = gpu_run(p, fl, steps, variant=0)
+    d = _kernel_diff(f3, f0)
+    log("band vs fused kernel: max diff %.2e" % d)
+    assert d <= 1e-13
+
+
+@pytest.mark.parametrize("axis", ["y", "x"])
+def test_band_kernel_walls(axis):
+    """NEQ walls in the band kernel: on the rows of a 600 x 5 channel, or on
+    the first and last columns of a 700 x 3 one."""
+    if axis == "y":
+        p, fl, _ = inputs.couette(0.7, nx=600, ny=5, dt_over_dy=0.05)
+    else:
+        p, fl, _ = inputs.couette_x(2.0, nx=700, ny=3)
+    steps = 1001
+    log("band kernel, NEQ walls on %s, %dx%d, %d steps" % (axis, p["nx"], p["ny"], steps))
+    g, f3 = gpu_run(p, fl, steps, variant=3)
+    o, _ = oracle_run(p, fl, steps)
+    assert_parity(g, o, what="band walls on " + axis)
+    _, f0 = gpu_run(p, fl, steps, variant=0)
+    d = _kernel_diff(f3, f0)
+    log("band vs fused kernel: max diff %.2e" % d)
+    assert d <= 1e-12
+
+
+def test_band_variant_is_rejected_where_it_does_not_apply():
+    from paper_1106_0785_amd import lbm
+
+    for nx, ny, scheme in [(100, 17, 0), (20, 20, 0), (300, 4, 1)]:
+        p, fl = _small(9, nx, ny, ["periodic"] * 4)
+        p["scheme"] = scheme
+        sim = lbm.Simulation(p)
+        with pytest.raises(lbm.LbmError):
+            sim.set_variant(3)
+        sim.close()
