@@ -11,6 +11,7 @@
 
 #include "../../include/lbm.h"
 #include "lbm_internal.h"
+#include "lbm_multistep.h"
 
 using namespace lbm;
 
