@@ -141,10 +141,10 @@ lbm_status lbm_check(lbm_handle* h);
  *   2 the small-grid kernel (default when nx ny <= 512 and scheme 0;
  *     LBM_EINVAL otherwise): one workgroup holds the whole grid in LDS and
  *     takes up to 65536 steps per launch;
- *   3 the narrow-grid kernel (default when ny <= 16, nx ny > 512 and scheme
- *     0; LBM_EINVAL otherwise): workgroups hold overlapping windows of 64
- *     columns (32 when ny > 8) by all rows in LDS and take up to 8 (4) steps
- *     per launch, recomputing the overlap.
+ *   3 the windowed kernel (scheme 0 and nx ny > 512, LBM_EINVAL otherwise;
+ *     default when ny <= 16): workgroups hold overlapping windows of the grid
+ *     in LDS (lbm_set_window) and take several steps per launch,
+ *     recomputing the overlap.
  * Variants 2 and 3 take many steps per launch, so small and narrow grids are
  * not bound by launch cost. All variants give the same results to rounding.
  * lbm_set_tile sets the tile shape of variant 0:
@@ -153,6 +153,17 @@ lbm_status lbm_check(lbm_handle* h);
  * Results do not depend on the tile shape. */
 lbm_status lbm_set_variant(lbm_handle* h, int32_t variant);
 lbm_status lbm_set_tile(lbm_handle* h, int32_t rows, int32_t waves);
+
+/* Window shape of variant 3: cols x rows nodes held per workgroup (at most
+ * 512), steps = most time steps per launch. An axis no longer than the
+ * window is held whole; a longer one is cut into windows that overlap by
+ * `steps` nodes on each cut side, each writing its middle (extent - 2 steps)
+ * nodes, so cut extents must exceed 2 steps. Default: grids of <= 16 rows
+ * take every row and 64 columns (32 when ny > 8) with steps = columns / 8;
+ * other grids 32 x 16 with 2 steps. Results do not depend on the shape
+ * beyond rounding. */
+lbm_status lbm_set_window(lbm_handle* h, int32_t cols, int32_t rows, int32_t steps);
+lbm_status lbm_get_window(const lbm_handle* h, int32_t* cols, int32_t* rows, int32_t* steps);
 
 /* Tile-shape tuner for variant 0: times probe_steps steps for each
  * candidate (wavefronts per workgroup x tile height), synchronising the

@@ -181,33 +181,66 @@ hipError_t launch_small(const Field& F, const Hot* c, const Cold* cold, int vers
   return hipGetLastError();
 }
 
-// True when the grid takes the narrow-grid (band) kernel: scheme 0, too big
-// for the small-grid kernel, at most 16 rows.
-bool band_problem(const lbm_params* p) {
-  return p->scheme == 0 && !small_problem(p) && p->ny <= 16;
+// True when the windowed kernel applies: scheme 0 and too big for the
+// small-grid kernel.
+bool window_problem(const lbm_params* p) { return p->scheme == 0 && !small_problem(p); }
+
+// True when the windowed kernel is the default: narrow grids (<= 16 rows).
+bool narrow_problem(const lbm_params* p) { return window_problem(p) && p->ny <= 16; }
+
+// One axis of the window shape: the whole axis in one window when it fits,
+// else windows of w nodes writing w - 2 h each.
+WinAxis win_axis(int len, int w, int h) {
+  WinAxis a;
+  if (len <= w) {
+    a.w = len;
+    a.v = len;
+    a.nwin = 1;
+    a.whole = 1;
+  } else {
+    a.w = w;
+    a.v = w - 2 * h;
+    a.nwin = (len + a.v - 1) / a.v;
+    a.whole = 0;
+  }
+  return a;
 }
 
-// Window shape of the band kernel: 64 columns by ny <= 8 rows or 32 by ny
-// <= 16, h = wc / 8 steps per launch, the middle 3/4 of the columns written.
-BandGeom band_geom(int nx, int ny) {
-  BandGeom g;
-  g.wc = ny <= 8 ? 64 : 32;
-  g.h = g.wc / 8;
-  g.v = g.wc - 2 * g.h;
-  g.nwin = (nx + g.v - 1) / g.v;
+// Checks a window shape (wc columns, wr rows, h steps per launch) for an
+// nx-by-ny grid; fills g when it is valid.
+bool make_window(int nx, int ny, int wc, int wr, int h, WinGeom* g) {
+  if (h < 1 || wc < 1 || wr < 1) return false;
+  const WinAxis x = win_axis(nx, wc, h), y = win_axis(ny, wr, h);
+  if (x.v < 1 || y.v < 1) return false;
+  if ((long long)x.w * y.w > SMALL_NODES) return false;
+  g->x = x;
+  g->y = y;
+  g->h = h;
+  return true;
+}
+
+// Default window shape: narrow grids take every row and 64 columns (32 when
+// ny > 8), h = columns / 8; other grids 32 x 16 nodes, h = 2.
+WinGeom default_window(int nx, int ny) {
+  WinGeom g{};
+  if (ny <= 16) {
+    const int wc = ny <= 8 ? 64 : 32;
+    make_window(nx, ny, wc, ny, wc / 8, &g);
+  } else {
+    make_window(nx, ny, 32, 16, 2, &g);
+  }
   return g;
 }
 
-hipError_t launch_band(const Field& F, const Hot* c, const Cold* cold, int version, bool walls, int nsteps,
-                       int* flag, hipStream_t s) {
-  const BandGeom g = band_geom(F.nx, F.ny);
-  decltype(&k_step_band<1, false>) k;
+hipError_t launch_window(const Field& F, const Hot* c, const Cold* cold, int version, bool walls,
+                         const WinGeom& g, int nsteps, int* flag, hipStream_t s) {
+  decltype(&k_step_window<1, false>) k;
   if (walls)
-    k = version == 2 ? k_step_band<2, true> : version == 3 ? k_step_band<3, true> : k_step_band<1, true>;
+    k = version == 2 ? k_step_window<2, true> : version == 3 ? k_step_window<3, true> : k_step_window<1, true>;
   else
-    k = version == 2 ? k_step_band<2, false> : version == 3 ? k_step_band<3, false> : k_step_band<1, false>;
-  const int threads = (g.wc * F.ny + 63) / 64 * 64;
-  hipLaunchKernelGGL(k, dim3(g.nwin), dim3(threads), 0, s, F, c, cold, g, nsteps, flag);
+    k = version == 2 ? k_step_window<2, false> : version == 3 ? k_step_window<3, false> : k_step_window<1, false>;
+  const int threads = (g.x.w * g.y.w + 63) / 64 * 64;
+  hipLaunchKernelGGL(k, dim3(g.x.nwin * g.y.nwin), dim3(threads), 0, s, F, c, cold, g, nsteps, flag);
   return hipGetLastError();
 }
 
@@ -233,6 +266,7 @@ struct lbm_handle {
   long long pitch, plane;
   int variant;
   TileShape tile;
+  WinGeom win;  // window shape of variant 3
 };
 
 static Field field_of(const lbm_handle* h, int from) {
@@ -282,7 +316,8 @@ lbm_status lbm_create(const lbm_params* p, void* d_workspace, size_t ws_bytes, v
   h->flag = (int*)(base + 2 * 16 * h->plane * sizeof(double));
   h->dev = (Consts*)(base + 2 * 16 * h->plane * sizeof(double) + 256);
   h->cur = 0;
-  h->variant = small_problem(p) ? 2 : band_problem(p) ? 3 : 0;
+  h->variant = small_problem(p) ? 2 : narrow_problem(p) ? 3 : 0;
+  h->win = default_window(p->nx, p->ny);
   h->tile = default_tile(p->nx, p->ny);
   e = hipMemsetAsync(h->flag, 0, 256, h->stream);
   if (e == hipSuccess)
@@ -329,13 +364,13 @@ lbm_status lbm_step(lbm_handle* h, int64_t nsteps) {
     return LBM_OK;
   }
   if (h->variant == 3) {
-    // narrow grid: up to h steps per launch in LDS windows
-    const int64_t hmax = band_geom(h->p.nx, h->p.ny).h;
+    // up to win.h steps per launch in LDS windows
+    const int64_t hmax = h->win.h;
     for (int64_t n = 0; n < nsteps; n += hmax) {
       const int k = (int)std::min<int64_t>(hmax, nsteps - n);
-      hipError_t e = launch_band(field_of(h, h->cur), &h->dev->hot, &h->dev->cold, h->p.eq_version,
-                                 has_walls(&h->p), k, h->flag, h->stream);
-      if (e != hipSuccess) return hip_fail(e, "band kernel launch");
+      hipError_t e = launch_window(field_of(h, h->cur), &h->dev->hot, &h->dev->cold, h->p.eq_version,
+                                   has_walls(&h->p), h->win, k, h->flag, h->stream);
+      if (e != hipSuccess) return hip_fail(e, "windowed kernel launch");
       h->cur ^= 1;
     }
     return LBM_OK;
@@ -398,8 +433,8 @@ lbm_status lbm_set_variant(lbm_handle* h, int32_t variant) {
   if (variant < 0 || variant > 3) return fail(LBM_EINVAL, "variant must be 0, 1, 2 or 3");
   if (variant == 2 && !small_problem(&h->p))
     return fail(LBM_EINVAL, "variant 2 needs scheme 0 and nx ny <= %d nodes", SMALL_NODES);
-  if (variant == 3 && !band_problem(&h->p))
-    return fail(LBM_EINVAL, "variant 3 needs scheme 0, ny <= 16 and nx ny > %d nodes", SMALL_NODES);
+  if (variant == 3 && !window_problem(&h->p))
+    return fail(LBM_EINVAL, "variant 3 needs scheme 0 and nx ny > %d nodes", SMALL_NODES);
   h->variant = variant;
   return LBM_OK;
 }
@@ -409,6 +444,26 @@ lbm_status lbm_set_tile(lbm_handle* h, int32_t rows, int32_t waves) {
   if (rows < 1 || rows > 1024) return fail(LBM_EINVAL, "rows must be in 1..1024");
   if (waves != 2 && waves != 4) return fail(LBM_EINVAL, "waves must be 2 or 4");
   h->tile = TileShape{rows, has_walls(&h->p) ? 4 : waves};
+  return LBM_OK;
+}
+
+lbm_status lbm_set_window(lbm_handle* h, int32_t cols, int32_t rows, int32_t steps) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  WinGeom g;
+  if (!make_window(h->p.nx, h->p.ny, cols, rows, steps, &g))
+    return fail(LBM_EINVAL,
+                "window %d x %d with %d steps: need steps >= 1, a cut axis longer than 2 steps, "
+                "and at most %d nodes held",
+                cols, rows, steps, SMALL_NODES);
+  h->win = g;
+  return LBM_OK;
+}
+
+lbm_status lbm_get_window(const lbm_handle* h, int32_t* cols, int32_t* rows, int32_t* steps) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (cols) *cols = h->win.x.w;
+  if (rows) *rows = h->win.y.w;
+  if (steps) *steps = h->win.h;
   return LBM_OK;
 }
 

@@ -1,7 +1,8 @@
 // Multi-step kernels for grids that one launch per step leaves bound by
-// launch cost: the small-grid kernel (the whole grid in one workgroup's LDS)
-// and the narrow-grid kernel (overlapping LDS windows of all rows). Both use
-// the plain kernel's stencil, ghost rules and node arithmetic.
+// launch cost or latency: the small-grid kernel (the whole grid in one
+// workgroup's LDS) and the windowed kernel (overlapping LDS windows, several
+// steps per launch). Both use the plain kernel's stencil, ghost rules and
+// node arithmetic.
 #pragma once
 
 #include "lbm_kernels.h"
@@ -95,85 +96,122 @@ __global__ __launch_bounds__(SMALL_NODES) void k_step_small(Field F, const Hot* 
 }
 
 // ---------------------------------------------------------------------------
-// Narrow grids (few rows, many columns; more than SMALL_NODES nodes): each
-// workgroup holds a window of wc columns by all ny rows in LDS and advances
-// it up to h steps per launch (temporal blocking). Windows overlap by h
-// columns on each side that is cut from a neighbouring window; after k steps
-// a node is exact if it is at least k columns from every cut side, so the
-// middle v = wc - 2 h columns are written back. On a periodic x axis the
-// window columns are the periodic images of the stored ones (the update is
-// translation invariant); on other x boundaries the window is clipped to the
-// domain and the ghost rules apply at the domain edge, as in the other
-// kernels. Each node's arithmetic is the plain kernel's.
+// Windowed multi-step kernel: each workgroup holds a window of wc columns by
+// wr rows in LDS (one thread per node) and advances it up to h steps per
+// launch (temporal blocking). Along an axis that one window covers whole,
+// neighbours follow the ghost rules as in the other kernels. Along an axis
+// cut into windows, windows overlap by h nodes on each side cut from a
+// neighbouring window; after k steps a node is exact if it lies at least k
+// nodes from every cut side, so the middle (w - 2 h) nodes are written back
+// and those parts tile the axis. On a periodic cut axis the window holds the
+// periodic images of the stored nodes (the update is translation invariant);
+// on other cut axes windows are clipped to the domain and the ghost rules
+// apply at the domain edge. Narrow grids (few rows) use one window row.
+// Each node's arithmetic is the plain kernel's.
 // ---------------------------------------------------------------------------
-struct BandGeom {
-  int wc;    // window columns (wc ny <= SMALL_NODES)
-  int h;     // most steps per launch
-  int v;     // columns written per window: wc - 2 h
-  int nwin;  // windows: ceil(nx / v)
+struct WinAxis {
+  int w;      // window extent (nodes held); the whole axis when nwin == 1 and whole
+  int v;      // nodes written per window (w - 2 h on a cut axis)
+  int nwin;   // windows along the axis
+  int whole;  // 1: one window holds the whole axis (no cuts)
 };
 
+struct WinGeom {
+  WinAxis x, y;
+  int h;  // most steps per launch
+};
+
+// One axis of one window: held nodes [s, e) (virtual on a periodic cut
+// axis), the nodes it writes [o, o + v), and which sides are cuts.
+struct WinSpan {
+  int s, n, o, v;
+  bool lo_cut, hi_cut;
+};
+
+__device__ __forceinline__ WinSpan win_span(const WinAxis& a, int h, int win, int len, bool per) {
+  WinSpan r;
+  if (a.whole) {
+    r.s = 0;
+    r.n = len;
+    r.o = 0;
+    r.v = len;
+    r.lo_cut = r.hi_cut = false;
+    return r;
+  }
+  r.o = win * a.v;
+  r.v = a.v;
+  int s = r.o - h, e = r.o + a.v + h;
+  if (!per) {
+    s = max(s, 0);
+    e = min(e, len);
+  }
+  r.s = s;
+  r.n = e - s;
+  r.lo_cut = per || s > 0;
+  r.hi_cut = per || e < len;
+  return r;
+}
+
+// Neighbour (offset d = +-1) of local node w along one axis of a window:
+// local index and ghost treatment. At a cut side the node's own index is
+// returned: the node is outside the exact region from the first step on.
+__device__ __forceinline__ Src win_nbr(const WinSpan& sp, int w, int g, int d, int len, int bc_lo, int bc_hi,
+                                       int side, int& local) {
+  const int w2 = w + d;
+  if (w2 >= 0 && w2 < sp.n) {
+    local = w2;
+    return Src{w2, 0, -1};
+  }
+  if ((d < 0 && sp.lo_cut) || (d > 0 && sp.hi_cut)) {
+    local = w;
+    return Src{w, 0, -1};
+  }
+  const Src sg = resolve(g + d, len, bc_lo, bc_hi, side);
+  local = sg.idx - sp.s;
+  return sg;
+}
+
 template <int VER, bool WALLS>
-__global__ __launch_bounds__(SMALL_NODES) void k_step_band(Field F, const Hot* __restrict__ hot,
-                                                          const Cold* __restrict__ cold, BandGeom bg, int nsteps,
-                                                          int* flag) {
+__global__ __launch_bounds__(SMALL_NODES) void k_step_window(Field F, const Hot* __restrict__ hot,
+                                                            const Cold* __restrict__ cold, WinGeom wg, int nsteps,
+                                                            int* flag) {
   __shared__ double buf[2][16][SMALL_NODES];
   __shared__ Hot hs;
   stage_hot(hot, &hs);
   const Hot& c = hs;
-  const bool xper = c.bc[0] == BC_PERIODIC;
-  const int x0 = blockIdx.x * bg.v;  // first column this window writes
-  int xs = x0 - bg.h, xe = x0 + bg.v + bg.h;
-  if (!xper) {
-    xs = max(xs, 0);
-    xe = min(xe, F.nx);
-  }
-  const int ncols = xe - xs;
-  const bool lo_cut = xper || xs > 0, hi_cut = xper || xe < F.nx;
+  const bool xper = c.bc[0] == BC_PERIODIC, yper = c.bc[2] == BC_PERIODIC;
+  const WinSpan sx = win_span(wg.x, wg.h, blockIdx.x % wg.x.nwin, F.nx, xper);
+  const WinSpan sy = win_span(wg.y, wg.h, blockIdx.x / wg.x.nwin, F.ny, yper);
   const int t = threadIdx.x;
-  const bool active = t < ncols * F.ny;
-  const int xw = active ? t % ncols : 0, y = active ? t / ncols : 0;
-  const int xv = xs + xw;                                    // column (virtual on a periodic axis)
-  const int xg = xper ? ((xv % F.nx) + F.nx) % F.nx : xv;  // stored column
+  const bool active = t < sx.n * sy.n;
+  const int xw = active ? t % sx.n : 0, yw = active ? t / sx.n : 0;
+  const int xv = sx.s + xw, yv = sy.s + yw;  // virtual on a periodic cut axis
+  const int xg = xper ? ((xv % F.nx) + F.nx) % F.nx : xv;
+  const int yg = yper ? ((yv % F.ny) + F.ny) % F.ny : yv;
   if (active) {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) buf[0][i][t] = F.fin[i * F.plane + (long long)y * F.pitch + xg];
+    for (int i = 0; i < 16; ++i) buf[0][i][t] = F.fin[i * F.plane + (long long)yg * F.pitch + xg];
   }
   __syncthreads();
-  // x neighbours: inside the window; the ghost rule at a domain edge; at a
-  // cut side the node's own column (the node is outside the exact region
-  // from the first step on, and is neither written back nor checked)
-  auto xnbr = [&](int d, int& col) -> Src {
-    const int w2 = xw + d;
-    if (w2 >= 0 && w2 < ncols) {
-      col = w2;
-      return Src{w2, 0, -1};
-    }
-    if ((d < 0 && lo_cut) || (d > 0 && hi_cut)) {
-      col = xw;
-      return Src{xw, 0, -1};
-    }
-    const Src sg = resolve(xg + d, F.nx, c.bc[0], c.bc[1], 0);
-    col = sg.idx - xs;
-    return sg;
-  };
-  int cxp, cxm;
-  const Src sxp = xnbr(1, cxp), sxm = xnbr(-1, cxm);
-  const Src cx{xw, 0, -1}, cy = resolve(y, F.ny, c.bc[2], c.bc[3], 2);
-  const Src syp = resolve(y + 1, F.ny, c.bc[2], c.bc[3], 2), sym = resolve(y - 1, F.ny, c.bc[2], c.bc[3], 2);
-  auto point = [&](int b, int col, const Src& sx, const Src& sy, double* f) {
-    const int k = sy.idx * ncols + col;
+  int lxp, lxm, lyp, lym;
+  const Src nxp = win_nbr(sx, xw, xg, 1, F.nx, c.bc[0], c.bc[1], 0, lxp);
+  const Src nxm = win_nbr(sx, xw, xg, -1, F.nx, c.bc[0], c.bc[1], 0, lxm);
+  const Src nyp = win_nbr(sy, yw, yg, 1, F.ny, c.bc[2], c.bc[3], 2, lyp);
+  const Src nym = win_nbr(sy, yw, yg, -1, F.ny, c.bc[2], c.bc[3], 2, lym);
+  const Src cx{xw, 0, -1}, cy{yw, 0, -1};
+  auto point = [&](int b, int lx, int ly, const Src& gx, const Src& gy, double* f) {
+    const int k = ly * sx.n + lx;
 #pragma unroll
     for (int i = 0; i < 16; ++i) f[i] = buf[b][i][k];
-    fix_ghost(cold, sx, sy, f);
+    fix_ghost(cold, gx, gy, f);
   };
-  const bool wall = WALLS && active && is_wall_node(c, xg, y, F.nx, F.ny);
+  const bool wall = WALLS && active && is_wall_node(c, xg, yg, F.nx, F.ny);
   int wnb = 0, wside = 0;
   if (WALLS && wall) {
-    if (c.bc[2] == BC_NEQ_WALL && y == 0) { wnb = 1 * ncols + xw; wside = 2; }
-    else if (c.bc[3] == BC_NEQ_WALL && y == F.ny - 1) { wnb = (F.ny - 2) * ncols + xw; wside = 3; }
-    else if (c.bc[0] == BC_NEQ_WALL && xg == 0) { wnb = y * ncols + xw + 1; wside = 0; }
-    else { wnb = y * ncols + xw - 1; wside = 1; }
+    if (c.bc[2] == BC_NEQ_WALL && yg == 0) { wnb = (yw + 1) * sx.n + xw; wside = 2; }
+    else if (c.bc[3] == BC_NEQ_WALL && yg == F.ny - 1) { wnb = (yw - 1) * sx.n + xw; wside = 3; }
+    else if (c.bc[0] == BC_NEQ_WALL && xg == 0) { wnb = yw * sx.n + xw + 1; wside = 0; }
+    else { wnb = yw * sx.n + xw - 1; wside = 1; }
   }
   bool ok = true;
   int P = 0;
@@ -181,18 +219,19 @@ __global__ __launch_bounds__(SMALL_NODES) void k_step_band(Field F, const Hot* _
     const int Q = P ^ 1;
     if (active && !wall) {
       double f[16], fxp[16], fxm[16], fyp[16], fym[16];
-      point(P, xw, cx, cy, f);
-      point(P, cxp, sxp, cy, fxp);
-      point(P, cxm, sxm, cy, fxm);
-      point(P, xw, cx, syp, fyp);
-      point(P, xw, cx, sym, fym);
+      point(P, xw, yw, cx, cy, f);
+      point(P, lxp, yw, nxp, cy, fxp);
+      point(P, lxm, yw, nxm, cy, fxm);
+      point(P, xw, lyp, cx, nyp, fyp);
+      point(P, xw, lym, cx, nym, fym);
       NbrVel nv;
       velocity_of(fxp, nv.ux_xp, nv.uy_xp);
       velocity_of(fxm, nv.ux_xm, nv.uy_xm);
       velocity_of(fyp, nv.ux_yp, nv.uy_yp);
       velocity_of(fym, nv.ux_ym, nv.uy_ym);
       double out[16];
-      const bool exact = (!lo_cut || xw >= s) && (!hi_cut || xw < ncols - s);
+      const bool exact = (!sx.lo_cut || xw >= s) && (!sx.hi_cut || xw < sx.n - s) && (!sy.lo_cut || yw >= s) &&
+                         (!sy.hi_cut || yw < sy.n - s);
       ok &= node_update<VER>(c, f, fxp, fxm, fyp, fym, nv, out) || !exact;
 #pragma unroll
       for (int i = 0; i < 16; ++i) buf[Q][i][t] = out[i];
@@ -211,9 +250,10 @@ __global__ __launch_bounds__(SMALL_NODES) void k_step_band(Field F, const Hot* _
     }
     P = Q;
   }
-  if (active && xv >= x0 && xv < x0 + bg.v && xv >= 0 && xv < F.nx) {
+  if (active && xv >= sx.o && xv < sx.o + sx.v && xv >= 0 && xv < F.nx && yv >= sy.o && yv < sy.o + sy.v &&
+      yv >= 0 && yv < F.ny) {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) F.fout[i * F.plane + (long long)y * F.pitch + xg] = buf[P][i][t];
+    for (int i = 0; i < 16; ++i) F.fout[i * F.plane + (long long)yg * F.pitch + xg] = buf[P][i][t];
   }
   if (!ok) flag[0] = 1;
 }

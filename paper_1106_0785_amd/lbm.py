@@ -84,6 +84,9 @@ def load():
             "lbm_tune": ([P, ctypes.c_int64, P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int32),
                           ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
             "lbm_get_tile": ([P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+            "lbm_set_window": ([P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
+            "lbm_get_window": ([P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
             "lbm_last_error": ([], ctypes.c_char_p),
             "lbm_destroy": ([P], None),
             "lbm_stream_copy": ([P, P, ctypes.c_int32, ctypes.c_int32, P], ctypes.c_int),
@@ -190,6 +193,17 @@ def lbm_get_tile(h):
     return rows.value, waves.value
 
 
+def lbm_set_window(h, cols, rows, steps):
+    _check(load().lbm_set_window(h, int(cols), int(rows), int(steps)))
+
+
+def lbm_get_window(h):
+    """Returns (cols, rows, steps) of the windowed kernel (variant 3)."""
+    c, r, st = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(load().lbm_get_window(h, ctypes.byref(c), ctypes.byref(r), ctypes.byref(st)))
+    return c.value, r.value, st.value
+
+
 def lbm_destroy(h):
     load().lbm_destroy(h)
 
@@ -268,6 +282,12 @@ class Simulation:
 
     def tile(self):
         return lbm_get_tile(self.handle)
+
+    def set_window(self, cols, rows, steps):
+        lbm_set_window(self.handle, cols, rows, steps)
+
+    def window(self):
+        return lbm_get_window(self.handle)
 
     def tune(self, probe_steps=20, keep_state=True):
         """Pick the fastest tile shape (rows, waves); with keep_state the

@@ -399,3 +399,76 @@ def test_band_variant_is_rejected_where_it_does_not_apply():
         with pytest.raises(lbm.LbmError):
             sim.set_variant(3)
         sim.close()
+
+
+WINDOWS = {
+    "periodic_200x77_32x16h2": (["periodic"] * 4, {}, (200, 77), (32, 16, 2)),
+    "specular_130x60_16x32h3": (["specular", "specular", "zero_gradient", "zero_gradient"], {}, (130, 60), (16, 32, 3)),
+    "dirichlet_150x45_64x8h1": (["dirichlet_eq", "zero_gradient", "specular", "specular"], {}, (150, 45), (64, 8, 1)),
+    "periodic_v3_99x99_8x8h3": (["periodic"] * 4, {"eq_version": 3}, (99, 99), (8, 8, 3)),
+    "mixed_x_periodic_y_70x200_32x16h4": (["zero_gradient", "specular", "periodic", "periodic"], {"modified": 2},
+                                          (70, 200), (32, 16, 4)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(WINDOWS))
+def test_window_kernel_cut_both_axes(name):
+    """The windowed kernel with windows cut along both axes."""
+    bc, kw, (nx, ny), (wc, wr, h) = WINDOWS[name]
+    p, fl = _small(15, nx, ny, bc, **kw)
+    if bc[0] == "dirichlet_eq":
+        p["wall"][0] = [1.05, 0.02, 0.0, 1.02]
+    from paper_1106_0785_amd import lbm
+
+    steps = 101
+    sim = lbm.Simulation(p)
+    sim.set_variant(3)
+    sim.set_window(wc, wr, h)
+    sim.init(**fl)
+    sim.step(steps)
+    g = {k: v.cpu().numpy() for k, v in sim.moments().items()}
+    f3 = sim.get_f().cpu().numpy()
+    sim.check()
+    sim.close()
+    o, _ = oracle_run(p, fl, steps)
+    assert_parity(g, o, what="windows %s" % name)
+    _, f0 = gpu_run(p, fl, steps, variant=0)
+    d = _kernel_diff(f3, f0)
+    log("windows %s vs fused kernel: max diff %.2e" % (name, d))
+    assert d <= 1e-13
+
+
+@pytest.mark.parametrize("axis", ["y", "x"])
+def test_window_kernel_walls_on_a_cut_axis(axis):
+    """NEQ walls on an axis cut into windows (only the end windows hold
+    wall nodes)."""
+    from paper_1106_0785_amd import lbm
+
+    if axis == "y":
+        p, fl, _ = inputs.couette(0.7, nx=40, ny=64)
+    else:
+        p, fl, _ = inputs.couette_x(2.0, nx=64, ny=40)
+    steps = 1001
+    sim = lbm.Simulation(p)
+    sim.set_variant(3)
+    sim.set_window(16, 32, 3)
+    sim.init(**fl)
+    sim.step(steps)
+    g = {k: v.cpu().numpy() for k, v in sim.moments().items()}
+    sim.check()
+    sim.close()
+    o, _ = oracle_run(p, fl, steps)
+    assert_parity(g, o, what="windows, walls on " + axis)
+
+
+def test_window_shapes_are_checked():
+    from paper_1106_0785_amd import lbm
+
+    p, fl = _small(9, 100, 50, ["periodic"] * 4)
+    sim = lbm.Simulation(p)
+    for bad in [(32, 16, 0), (32, 32, 2), (4, 16, 2), (600, 1, 1)]:
+        with pytest.raises(lbm.LbmError):
+            sim.set_window(*bad)
+    sim.set_window(32, 16, 2)
+    assert sim.window() == (32, 16, 2)
+    sim.close()
