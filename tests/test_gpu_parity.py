@@ -389,10 +389,11 @@ def test_band_kernel_walls(axis):
     assert d <= 1e-12
 
 
-def test_band_variant_is_rejected_where_it_does_not_apply():
+def test_window_variant_is_rejected_where_it_does_not_apply():
+    """Variant 3 needs scheme 0 and more than 512 nodes."""
     from paper_1106_0785_amd import lbm
 
-    for nx, ny, scheme in [(100, 17, 0), (20, 20, 0), (300, 4, 1)]:
+    for nx, ny, scheme in [(16, 32, 0), (20, 20, 0), (300, 4, 1)]:
         p, fl = _small(9, nx, ny, ["periodic"] * 4)
         p["scheme"] = scheme
         sim = lbm.Simulation(p)
