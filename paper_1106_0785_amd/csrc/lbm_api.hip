@@ -200,7 +200,7 @@ WinAxis win_axis(int len, int w, int h) {
   } else {
     a.w = w;
     a.v = w - 2 * h;
-    a.nwin = (len + a.v - 1) / a.v;
+    a.nwin = a.v >= 1 ? (len + a.v - 1) / a.v : 0;  // v < 1: rejected by make_window
     a.whole = 0;
   }
   return a;
