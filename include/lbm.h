@@ -152,6 +152,7 @@ lbm_status lbm_check(lbm_handle* h);
  * wavefronts per workgroup (2 or 4; problems with NEQ walls always use 4).
  * Results do not depend on the tile shape. */
 lbm_status lbm_set_variant(lbm_handle* h, int32_t variant);
+lbm_status lbm_get_variant(const lbm_handle* h, int32_t* variant);
 lbm_status lbm_set_tile(lbm_handle* h, int32_t rows, int32_t waves);
 
 /* Window shape of variant 3: cols x rows nodes held per workgroup (at most
@@ -165,10 +166,15 @@ lbm_status lbm_set_tile(lbm_handle* h, int32_t rows, int32_t waves);
 lbm_status lbm_set_window(lbm_handle* h, int32_t cols, int32_t rows, int32_t steps);
 lbm_status lbm_get_window(const lbm_handle* h, int32_t* cols, int32_t* rows, int32_t* steps);
 
-/* Tile-shape tuner for variant 0: times probe_steps steps for each
- * candidate (wavefronts per workgroup x tile height), synchronising the
- * stream, and keeps the fastest (rows_out, waves_out, best_ms may be NULL).
- * With d_scratch (device, >= 16 ny pitch doubles) the state is saved and
+/* Tuner: times probe_steps steps for each candidate fused tile shape
+ * (wavefronts per workgroup x tile height) and keeps the fastest. When the
+ * handle uses variant 0 or 3 and the windowed kernel applies, it also times
+ * window shapes (every row for grids of <= 16 rows, two-dimensional windows
+ * otherwise) and then uses whichever kernel and shape was fastest
+ * (lbm_get_variant, lbm_get_window). Variants 1 and 2 are kept. Synchronises
+ * the stream. rows_out, waves_out: the fastest fused tile; best_ms: the best
+ * time of probe_steps steps over all candidates (each may be NULL). With
+ * d_scratch (device, >= 16 ny pitch doubles) the state is saved and
  * restored; with NULL the state advances. */
 lbm_status lbm_tune(lbm_handle* h, int64_t probe_steps, double* d_scratch, size_t scratch_bytes, int32_t* rows_out,
                     int32_t* waves_out, double* best_ms);

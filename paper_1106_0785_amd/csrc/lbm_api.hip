@@ -477,50 +477,86 @@ lbm_status lbm_tune(lbm_handle* h, int64_t probe_steps, double* d_scratch, size_
   if (d_scratch) e = hipMemcpyAsync(d_scratch, h->f[h->cur], state, hipMemcpyDeviceToDevice, h->stream);
   if (e != hipSuccess) return hip_fail(e, "saving the state");
   const int saved_cur = h->cur, saved_variant = h->variant;
-  h->variant = 0;
+  // the windowed kernel competes with the fused one unless another variant was chosen
+  const bool windows = window_problem(&h->p) && (saved_variant == 0 || saved_variant == 3);
   hipEvent_t t0 = nullptr, t1 = nullptr;
   e = hipEventCreate(&t0);
   if (e == hipSuccess) e = hipEventCreate(&t1);
   if (e != hipSuccess) {
     if (t0) (void)hipEventDestroy(t0);
-    h->variant = saved_variant;
     return hip_fail(e, "hipEventCreate");
   }
+  lbm_status st = LBM_OK;
+  // probe_steps steps of the current configuration after a 2-step warm-up
+  auto time_it = [&](float& ms) -> bool {
+    st = lbm_step(h, 2);
+    if (st != LBM_OK) return false;
+    e = hipEventRecord(t0, h->stream);
+    if (e == hipSuccess) st = lbm_step(h, probe_steps);
+    if (e == hipSuccess) e = hipEventRecord(t1, h->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(t1);
+    if (e == hipSuccess && st == LBM_OK) e = hipEventElapsedTime(&ms, t0, t1);
+    return e == hipSuccess && st == LBM_OK;
+  };
   const int cand[] = {4, 8, 12, 16, 20, 24, 28, 32, 40, 48, 56, 64, 96, 128, 192, 256};
   const int wcand[] = {4, 2};
   TileShape best = h->tile;
   float best_t = 1e30f;
-  lbm_status st = LBM_OK;
+  WinGeom best_win = h->win;
+  float best_win_t = 1e30f;
+  bool good = true;
+  h->variant = 0;
   for (int wv : wcand) {
     if (wv != 4 && has_walls(&h->p)) continue;
     int last_rows = -1;
     for (int r : cand) {
-      const TileShape t{r, wv};
-      const MarchGeom g = march_geom(h->p.nx, h->p.ny, t);
+      const MarchGeom g = march_geom(h->p.nx, h->p.ny, TileShape{r, wv});
       if (g.rows == last_rows) continue;  // same tiling as a smaller candidate
       last_rows = g.rows;
       h->tile = TileShape{g.rows, wv};
-      st = lbm_step(h, 2);  // warm-up
-      if (st != LBM_OK) break;
-      e = hipEventRecord(t0, h->stream);
-      if (e == hipSuccess) st = lbm_step(h, probe_steps);
-      if (e == hipSuccess) e = hipEventRecord(t1, h->stream);
-      if (e == hipSuccess) e = hipEventSynchronize(t1);
-      if (e != hipSuccess || st != LBM_OK) break;
       float ms = 0;
-      e = hipEventElapsedTime(&ms, t0, t1);
-      if (e != hipSuccess) break;
+      if (!(good = time_it(ms))) break;
       if (ms < best_t) {
         best_t = ms;
         best = h->tile;
       }
     }
-    if (e != hipSuccess || st != LBM_OK) break;
+    if (!good) break;
+  }
+  h->tile = best;
+  if (good && windows) {
+    // window shapes: narrow grids keep every row; others take 2-D windows
+    int shapes[24][3];
+    int ns = 0;
+    if (h->p.ny <= 16) {
+      for (int wc = 32; wc <= SMALL_NODES; wc *= 2)
+        for (int div : {16, 8, 4})
+          if (ns < 24) shapes[ns][0] = wc, shapes[ns][1] = h->p.ny, shapes[ns][2] = wc / div, ++ns;
+    } else {
+      const int two_d[][3] = {{32, 16, 2}, {32, 16, 3}, {16, 32, 2}, {16, 32, 3},
+                              {32, 8, 2},  {64, 8, 2},  {16, 16, 2}, {16, 16, 3}};
+      for (const auto& c3 : two_d) shapes[ns][0] = c3[0], shapes[ns][1] = c3[1], shapes[ns][2] = c3[2], ++ns;
+    }
+    h->variant = 3;
+    for (int i = 0; i < ns && good; ++i) {
+      WinGeom g;
+      if (!make_window(h->p.nx, h->p.ny, shapes[i][0], shapes[i][1], shapes[i][2], &g)) continue;
+      h->win = g;
+      float ms = 0;
+      if (!(good = time_it(ms))) break;
+      if (ms < best_win_t) {
+        best_win_t = ms;
+        best_win = g;
+      }
+    }
+    h->win = best_win;
   }
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
-  h->variant = saved_variant;
-  h->tile = best;
+  if (windows)
+    h->variant = best_win_t < best_t ? 3 : 0;
+  else
+    h->variant = saved_variant;
   if (e != hipSuccess) return hip_fail(e, "tuning run");
   if (st != LBM_OK) return st;
   if (d_scratch) {
@@ -531,7 +567,13 @@ lbm_status lbm_tune(lbm_handle* h, int64_t probe_steps, double* d_scratch, size_
   }
   if (rows_out) *rows_out = best.rows;
   if (waves_out) *waves_out = best.waves;
-  if (best_ms) *best_ms = best_t;
+  if (best_ms) *best_ms = std::min(best_t, best_win_t);
+  return LBM_OK;
+}
+
+lbm_status lbm_get_variant(const lbm_handle* h, int32_t* variant) {
+  if (!h || !variant) return fail(LBM_EINVAL, "NULL argument");
+  *variant = h->variant;
   return LBM_OK;
 }
 

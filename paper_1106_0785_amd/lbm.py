@@ -84,6 +84,7 @@ def load():
             "lbm_tune": ([P, ctypes.c_int64, P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int32),
                           ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
             "lbm_get_tile": ([P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+            "lbm_get_variant": ([P, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
             "lbm_set_window": ([P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
             "lbm_get_window": ([P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                 ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
@@ -193,6 +194,12 @@ def lbm_get_tile(h):
     return rows.value, waves.value
 
 
+def lbm_get_variant(h):
+    v = ctypes.c_int32()
+    _check(load().lbm_get_variant(h, ctypes.byref(v)))
+    return v.value
+
+
 def lbm_set_window(h, cols, rows, steps):
     _check(load().lbm_set_window(h, int(cols), int(rows), int(steps)))
 
@@ -282,6 +289,9 @@ class Simulation:
 
     def tile(self):
         return lbm_get_tile(self.handle)
+
+    def variant(self):
+        return lbm_get_variant(self.handle)
 
     def set_window(self, cols, rows, steps):
         lbm_set_window(self.handle, cols, rows, steps)

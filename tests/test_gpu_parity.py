@@ -473,3 +473,31 @@ def test_window_shapes_are_checked():
     sim.set_window(32, 16, 2)
     assert sim.window() == (32, 16, 2)
     sim.close()
+
+
+@pytest.mark.parametrize("case", ["sod_2000x4", "rm_256x64", "rm_300x100"])
+def test_tuner_picks_a_kernel_and_keeps_the_state(case):
+    """The tuner times fused tile shapes and window shapes, keeps the
+    fastest kernel, and restores the state; the run that follows matches
+    the oracle."""
+    from paper_1106_0785_amd import lbm
+
+    if case == "sod_2000x4":
+        p, fl, _ = inputs.riemann("sod", Pr=1.0, nx=2000, ny=4)
+    else:
+        nx, ny = (256, 64) if case == "rm_256x64" else (300, 100)
+        p, fl, _ = inputs.rm(seed=8, nx=nx, ny=ny)
+    sim = lbm.Simulation(p)
+    sim.init(**fl)
+    f0 = sim.get_f().cpu().numpy()
+    sim.tune(probe_steps=8)
+    variant = sim.variant()
+    log("tuner on %s: variant %d, window %s, tile %s" % (case, variant, sim.window(), sim.tile()))
+    assert variant in (0, 3)
+    assert np.array_equal(sim.get_f().cpu().numpy(), f0)
+    sim.step(100)
+    g = {k: v.cpu().numpy() for k, v in sim.moments().items()}
+    sim.check()
+    sim.close()
+    o, _ = oracle_run(p, fl, 100)
+    assert_parity(g, o, what="after tuning, " + case)
