@@ -175,7 +175,8 @@ template <int VER, bool WALLS>
 __global__ __launch_bounds__(SMALL_NODES) void k_step_window(Field F, const Hot* __restrict__ hot,
                                                             const Cold* __restrict__ cold, WinGeom wg, int nsteps,
                                                             int* flag) {
-  __shared__ double buf[2][16][SMALL_NODES];
+  // 16 distributions and the velocity of every held node, two buffers
+  __shared__ double buf[2][NV][SMALL_NODES];
   __shared__ Hot hs;
   stage_hot(hot, &hs);
   const Hot& c = hs;
@@ -188,9 +189,20 @@ __global__ __launch_bounds__(SMALL_NODES) void k_step_window(Field F, const Hot*
   const int xv = sx.s + xw, yv = sy.s + yw;  // virtual on a periodic cut axis
   const int xg = xper ? ((xv % F.nx) + F.nx) % F.nx : xv;
   const int yg = yper ? ((yv % F.ny) + F.ny) % F.ny : yv;
-  if (active) {
+  // a node's distributions and velocity into buffer b
+  auto put = [&](int b, const double* f) {
+    double ux, uy;
+    velocity_of(f, ux, uy);
 #pragma unroll
-    for (int i = 0; i < 16; ++i) buf[0][i][t] = F.fin[i * F.plane + (long long)yg * F.pitch + xg];
+    for (int i = 0; i < 16; ++i) buf[b][i][t] = f[i];
+    buf[b][16][t] = ux;
+    buf[b][17][t] = uy;
+  };
+  if (active) {
+    double f[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) f[i] = F.fin[i * F.plane + (long long)yg * F.pitch + xg];
+    put(0, f);
   }
   __syncthreads();
   int lxp, lxm, lyp, lym;
@@ -199,11 +211,19 @@ __global__ __launch_bounds__(SMALL_NODES) void k_step_window(Field F, const Hot*
   const Src nyp = win_nbr(sy, yw, yg, 1, F.ny, c.bc[2], c.bc[3], 2, lyp);
   const Src nym = win_nbr(sy, yw, yg, -1, F.ny, c.bc[2], c.bc[3], 2, lym);
   const Src cx{xw, 0, -1}, cy{yw, 0, -1};
-  auto point = [&](int b, int lx, int ly, const Src& gx, const Src& gy, double* f) {
+  // a neighbour's distributions and velocity: the stored velocity, or, for
+  // a ghost point, the velocity of the ghost distributions
+  auto point = [&](int b, int lx, int ly, const Src& gx, const Src& gy, double* f, double& ux, double& uy) {
     const int k = ly * sx.n + lx;
 #pragma unroll
     for (int i = 0; i < 16; ++i) f[i] = buf[b][i][k];
-    fix_ghost(cold, gx, gy, f);
+    if ((gx.mode | gy.mode) != 0) {
+      fix_ghost(cold, gx, gy, f);
+      velocity_of(f, ux, uy);
+    } else {
+      ux = buf[b][16][k];
+      uy = buf[b][17][k];
+    }
   };
   const bool wall = WALLS && active && is_wall_node(c, xg, yg, F.nx, F.ny);
   int wnb = 0, wside = 0;
@@ -219,22 +239,19 @@ __global__ __launch_bounds__(SMALL_NODES) void k_step_window(Field F, const Hot*
     const int Q = P ^ 1;
     if (active && !wall) {
       double f[16], fxp[16], fxm[16], fyp[16], fym[16];
-      point(P, xw, yw, cx, cy, f);
-      point(P, lxp, yw, nxp, cy, fxp);
-      point(P, lxm, yw, nxm, cy, fxm);
-      point(P, xw, lyp, cx, nyp, fyp);
-      point(P, xw, lym, cx, nym, fym);
+      const int k0 = yw * sx.n + xw;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) f[i] = buf[P][i][k0];
       NbrVel nv;
-      velocity_of(fxp, nv.ux_xp, nv.uy_xp);
-      velocity_of(fxm, nv.ux_xm, nv.uy_xm);
-      velocity_of(fyp, nv.ux_yp, nv.uy_yp);
-      velocity_of(fym, nv.ux_ym, nv.uy_ym);
+      point(P, lxp, yw, nxp, cy, fxp, nv.ux_xp, nv.uy_xp);
+      point(P, lxm, yw, nxm, cy, fxm, nv.ux_xm, nv.uy_xm);
+      point(P, xw, lyp, cx, nyp, fyp, nv.ux_yp, nv.uy_yp);
+      point(P, xw, lym, cx, nym, fym, nv.ux_ym, nv.uy_ym);
       double out[16];
       const bool exact = (!sx.lo_cut || xw >= s) && (!sx.hi_cut || xw < sx.n - s) && (!sy.lo_cut || yw >= s) &&
                          (!sy.hi_cut || yw < sy.n - s);
       ok &= node_update<VER>(c, f, fxp, fxm, fyp, fym, nv, out) || !exact;
-#pragma unroll
-      for (int i = 0; i < 16; ++i) buf[Q][i][t] = out[i];
+      put(Q, out);
     }
     __syncthreads();
     if (WALLS) {
@@ -243,8 +260,7 @@ __global__ __launch_bounds__(SMALL_NODES) void k_step_window(Field F, const Hot*
 #pragma unroll
         for (int i = 0; i < 16; ++i) fn[i] = buf[Q][i][wnb];
         neq_wall<VER>(cold->wall[wside], fn, fw);
-#pragma unroll
-        for (int i = 0; i < 16; ++i) buf[Q][i][t] = fw[i];
+        put(Q, fw);
       }
       __syncthreads();
     }
