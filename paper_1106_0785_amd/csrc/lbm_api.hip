@@ -234,12 +234,23 @@ WinGeom default_window(int nx, int ny) {
 
 hipError_t launch_window(const Field& F, const Hot* c, const Cold* cold, int version, bool walls,
                          const WinGeom& g, int nsteps, int* flag, hipStream_t s) {
-  decltype(&k_step_window<1, false>) k;
-  if (walls)
-    k = version == 2 ? k_step_window<2, true> : version == 3 ? k_step_window<3, true> : k_step_window<1, true>;
-  else
-    k = version == 2 ? k_step_window<2, false> : version == 3 ? k_step_window<3, false> : k_step_window<1, false>;
+  decltype(&k_step_window<1, false, SMALL_NODES>) k;
   const int threads = (g.x.w * g.y.w + 63) / 64 * 64;
+  if (threads <= SMALL_NODES / 2) {  // half the LDS: two workgroups per CU
+    if (walls)
+      k = version == 2 ? k_step_window<2, true, SMALL_NODES / 2>
+                       : version == 3 ? k_step_window<3, true, SMALL_NODES / 2> : k_step_window<1, true, SMALL_NODES / 2>;
+    else
+      k = version == 2 ? k_step_window<2, false, SMALL_NODES / 2>
+                       : version == 3 ? k_step_window<3, false, SMALL_NODES / 2>
+                                      : k_step_window<1, false, SMALL_NODES / 2>;
+  } else if (walls) {
+    k = version == 2 ? k_step_window<2, true, SMALL_NODES>
+                     : version == 3 ? k_step_window<3, true, SMALL_NODES> : k_step_window<1, true, SMALL_NODES>;
+  } else {
+    k = version == 2 ? k_step_window<2, false, SMALL_NODES>
+                     : version == 3 ? k_step_window<3, false, SMALL_NODES> : k_step_window<1, false, SMALL_NODES>;
+  }
   hipLaunchKernelGGL(k, dim3(g.x.nwin * g.y.nwin), dim3(threads), 0, s, F, c, cold, g, nsteps, flag);
   return hipGetLastError();
 }

@@ -171,12 +171,14 @@ __device__ __forceinline__ Src win_nbr(const WinSpan& sp, int w, int g, int d, i
   return sg;
 }
 
-template <int VER, bool WALLS>
-__global__ __launch_bounds__(SMALL_NODES) void k_step_window(Field F, const Hot* __restrict__ hot,
-                                                            const Cold* __restrict__ cold, WinGeom wg, int nsteps,
-                                                            int* flag) {
+// NODES: most nodes a window holds (512, or 256 so that two workgroups
+// share a CU's LDS).
+template <int VER, bool WALLS, int NODES>
+__global__ __launch_bounds__(NODES) void k_step_window(Field F, const Hot* __restrict__ hot,
+                                                      const Cold* __restrict__ cold, WinGeom wg, int nsteps,
+                                                      int* flag) {
   // 16 distributions and the velocity of every held node, two buffers
-  __shared__ double buf[2][NV][SMALL_NODES];
+  __shared__ double buf[2][NV][NODES];
   __shared__ Hot hs;
   stage_hot(hot, &hs);
   const Hot& c = hs;
