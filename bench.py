@@ -332,7 +332,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--quick", action="store_true", help="headline workload only")
-    ap.add_argument("--only", choices=["batch", "batch2d", "adjoint", "adjoint_hbm", "limited", "stability", "couette"], help="run one side measurement alone and print "
+    ap.add_argument("--only", choices=["batch", "batch2d", "adjoint", "adjoint_hbm", "limited", "stability", "couette", "riemann"], help="run one side measurement alone and print "
                     "its JSON (for profiling; not the benchmark line)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -364,6 +364,10 @@ def main():
     if args.only == "couette":
         pc, flc, _ = inputs.couette(1.0)
         print(json.dumps(run_problem(pc, flc, 20000, 100)), flush=True)
+        return
+    if args.only == "riemann":
+        pr, flr, _ = inputs.riemann("sod", nx=2000, ny=4)
+        print(json.dumps(run_problem(pr, flr, 20000, 100, tune=True)), flush=True)
         return
     if args.only == "limited":
         pl, fll, _ = inputs.rm(seed=0, nx=4096, ny=1024, width_cells=0.5)
