@@ -25,7 +25,9 @@ def _tuned_run(p, fl, steps):
 
     sim = lbm.Simulation(p)
     sim.init(**fl)
-    shape = sim.tune(probe_steps=4)
+    tile = sim.tune(probe_steps=4)
+    # the kernel and shape the tuner kept
+    shape = ("window", sim.window()) if sim.variant() == 3 else ("tile", tile[:2])
     sim.step(steps)
     out = {k: v.cpu().numpy() for k, v in sim.moments().items()}
     sim.check()
@@ -37,7 +39,7 @@ def test_headline_size_every_node():
     p, fl, _ = inputs.rm(seed=0, nx=4096, ny=1024)
     g, shape = _tuned_run(p, fl, 6)
     o, _ = oracle_run(p, fl, 6)
-    log("4096x1024, tuned tile %s, 6 steps" % (shape[:2],))
+    log("4096x1024, tuned %s %s, 6 steps" % shape)
     assert_parity(g, o, what="rm 4096x1024 6 steps")
 
 
@@ -45,7 +47,7 @@ def test_rm_1024x256_full_run():
     p, fl, _ = inputs.rm(seed=0, nx=1024, ny=256)
     g, shape = _tuned_run(p, fl, 5000)
     o, _ = oracle_run(p, fl, 5000)
-    log("1024x256, tuned tile %s, 5000 steps" % (shape[:2],))
+    log("1024x256, tuned %s %s, 5000 steps" % shape)
     assert_parity(g, o, what="rm 1024x256 5000 steps")
 
 
@@ -140,3 +142,29 @@ def test_grid_beyond_32_bit_offsets():
     del m
     sim.close()
     torch.cuda.empty_cache()
+
+
+def test_sod_2000x4_tuned_full_run():
+    """The 2000 x 4 Sod tube for its full 20 000 steps in the kernel and
+    shape the tuner picks (the benchmark's configuration: windows of all
+    rows, several steps per launch); the oracle runs the y-uniform problem
+    on one row."""
+    p, fl, _ = inputs.riemann("sod", Pr=1.0, nx=2000, ny=4)
+    g, shape = _tuned_run(p, fl, 20000)
+    p1, fl1, _ = inputs.riemann("sod", Pr=1.0, nx=2000, ny=1)
+    o, _ = oracle_run(p1, fl1, 20000)
+    log("sod 2000x4, tuned %s %s, 20000 steps" % shape)
+    for j in range(4):
+        assert_parity({k: v[j:j + 1] for k, v in g.items()}, o, what="sod 2000x4 row %d" % j)
+
+
+def test_limited_scheme_headline_size_every_node():
+    """The flux-limited scheme on the 4096 x 1024 sharp-interface problem
+    (the benchmark's side measurement), tuned tile, every node after 4
+    steps."""
+    p, fl, _ = inputs.rm(seed=0, nx=4096, ny=1024, width_cells=0.5)
+    p["scheme"] = 1
+    g, shape = _tuned_run(p, fl, 4)
+    o, _ = oracle_run(p, fl, 4)
+    log("limited 4096x1024, tuned %s %s, 4 steps" % shape)
+    assert_parity(g, o, what="limited 4096x1024 4 steps")
