@@ -75,6 +75,7 @@ def run_problem(p, fields, steps, warmup, rows=None, tune=False):
     nodes = p["nx"] * p["ny"]
     variant = sim.variant()
     window = sim.window() if variant == 3 else None
+    stores = "nontemporal" if sim.store_mode() else "ordinary"
     sim.close()
     out = {"seconds": t, "steps": steps, "nodes": nodes, "mlups": nodes * steps / t / 1e6,
            "ms_per_step": 1e3 * t / steps, "gbps": nodes * steps * BYTES_PER_NODE / t / 1e9,
@@ -83,6 +84,8 @@ def run_problem(p, fields, steps, warmup, rows=None, tune=False):
         out["window_cols"], out["window_rows"], out["window_steps"] = window
     elif tuned:
         out["tile_rows"], out["tile_waves"] = tuned[0], tuned[1]
+    if variant == 0:
+        out["stores"] = stores
     return out
 
 
@@ -415,7 +418,7 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                 "frac": round(achieved * 1e9 / HBM_PEAK, 4), "traffic": traffic_from_profiles(kernel, workload),
                 "kernel": kernel, "algorithmic_bytes_per_launch": bytes_per_launch,
-                "tile_rows": head.get("tile_rows"), "tile_waves": head.get("tile_waves")}
+                "tile_rows": head.get("tile_rows"), "tile_waves": head.get("tile_waves"), "stores": head.get("stores")}
     out = {
         "metric": "MLUPS (FP64 node updates/s) and fraction of HBM roofline",
         "value": round(head["mlups"], 1),

@@ -155,6 +155,14 @@ lbm_status lbm_set_variant(lbm_handle* h, int32_t variant);
 lbm_status lbm_get_variant(const lbm_handle* h, int32_t* variant);
 lbm_status lbm_set_tile(lbm_handle* h, int32_t rows, int32_t waves);
 
+/* Stores of the fused kernel (variant 0): nontemporal = 1 marks the new
+ * distributions as not to be kept in the caches, 0 uses ordinary stores
+ * (better while both distribution buffers fit in the caches, so the next
+ * step reads them back from there). Default: 0 when the two buffers take at
+ * most 512 MB, else 1; lbm_tune times both. Results do not depend on it. */
+lbm_status lbm_set_store_mode(lbm_handle* h, int32_t nontemporal);
+lbm_status lbm_get_store_mode(const lbm_handle* h, int32_t* nontemporal);
+
 /* Window shape of variant 3: cols x rows nodes held per workgroup (at most
  * 512), steps = most time steps per launch. An axis no longer than the
  * window is held whole; a longer one is cut into windows that overlap by
@@ -167,7 +175,8 @@ lbm_status lbm_set_window(lbm_handle* h, int32_t cols, int32_t rows, int32_t ste
 lbm_status lbm_get_window(const lbm_handle* h, int32_t* cols, int32_t* rows, int32_t* steps);
 
 /* Tuner: times probe_steps steps for each candidate fused tile shape
- * (wavefronts per workgroup x tile height) and keeps the fastest. When the
+ * (wavefronts per workgroup x tile height x store mode) and keeps the
+ * fastest. When the
  * handle uses variant 0 or 3 and the windowed kernel applies, it also times
  * window shapes (every row for grids of <= 16 rows, two-dimensional windows
  * otherwise) and then uses whichever kernel and shape was fastest

@@ -147,19 +147,21 @@ hipError_t launch_step(const Field& F, const Hot* c, const Cold* cold, int versi
   // NEQ walls and the flux-limited scheme use 4-wave tiles
   if (walls || scheme == 1 || t.waves != 2) t.waves = 4;
   const MarchGeom g = march_geom(F.nx, F.ny, t);
-  decltype(&k_step_fused<1, false, 4, 1>) k;
+  decltype(&k_step_fused<1, false, 4, 1, true>) k;
+#define LBM_FUSED(WALLS, W, HR)                                                                            \
+  k = t.nt ? (version == 2 ? k_step_fused<2, WALLS, W, HR, true>                                          \
+                           : version == 3 ? k_step_fused<3, WALLS, W, HR, true> : k_step_fused<1, WALLS, W, HR, true>) \
+           : (version == 2 ? k_step_fused<2, WALLS, W, HR, false>                                         \
+                           : version == 3 ? k_step_fused<3, WALLS, W, HR, false> : k_step_fused<1, WALLS, W, HR, false>)
   if (walls)
-    k = version == 2 ? k_step_fused<2, true, 4, 1> : version == 3 ? k_step_fused<3, true, 4, 1>
-                                                                    : k_step_fused<1, true, 4, 1>;
+    LBM_FUSED(true, 4, 1);
   else if (scheme == 1)
-    k = version == 2 ? k_step_fused<2, false, 4, 2> : version == 3 ? k_step_fused<3, false, 4, 2>
-                                                                     : k_step_fused<1, false, 4, 2>;
+    LBM_FUSED(false, 4, 2);
   else if (t.waves == 2)
-    k = version == 2 ? k_step_fused<2, false, 2, 1> : version == 3 ? k_step_fused<3, false, 2, 1>
-                                                                     : k_step_fused<1, false, 2, 1>;
+    LBM_FUSED(false, 2, 1);
   else
-    k = version == 2 ? k_step_fused<2, false, 4, 1> : version == 3 ? k_step_fused<3, false, 4, 1>
-                                                                     : k_step_fused<1, false, 4, 1>;
+    LBM_FUSED(false, 4, 1);
+#undef LBM_FUSED
   hipLaunchKernelGGL(k, dim3(8 * g.per_xcd), dim3(64 * t.waves), 0, s, F, c, cold, g, flag);
   return hipGetLastError();
 }
@@ -260,7 +262,10 @@ TileShape default_tile(int nx, int ny) {
   const long long strips = (nx + STRIP - 1) / STRIP;
   int rows = 64;
   while (rows > WAVES && strips * ((ny + rows - 1) / rows) < 1024) rows /= 2;
-  return TileShape{rows, WAVES};
+  // ordinary stores while both buffers (256 bytes per node) fit in 512 MB
+  // (measured: faster up to 2048 x 512, slower at 4096 x 1024)
+  const int nt = (long long)nx * ny * 256 > (512ll << 20) ? 1 : 0;
+  return TileShape{rows, WAVES, nt};
 }
 
 }  // namespace lbm
@@ -454,7 +459,20 @@ lbm_status lbm_set_tile(lbm_handle* h, int32_t rows, int32_t waves) {
   if (!h) return fail(LBM_EINVAL, "handle is NULL");
   if (rows < 1 || rows > 1024) return fail(LBM_EINVAL, "rows must be in 1..1024");
   if (waves != 2 && waves != 4) return fail(LBM_EINVAL, "waves must be 2 or 4");
-  h->tile = TileShape{rows, has_walls(&h->p) ? 4 : waves};
+  h->tile = TileShape{rows, has_walls(&h->p) ? 4 : waves, h->tile.nt};
+  return LBM_OK;
+}
+
+lbm_status lbm_set_store_mode(lbm_handle* h, int32_t nontemporal) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (nontemporal != 0 && nontemporal != 1) return fail(LBM_EINVAL, "nontemporal must be 0 or 1");
+  h->tile.nt = nontemporal;
+  return LBM_OK;
+}
+
+lbm_status lbm_get_store_mode(const lbm_handle* h, int32_t* nontemporal) {
+  if (!h || !nontemporal) return fail(LBM_EINVAL, "NULL argument");
+  *nontemporal = h->tile.nt;
   return LBM_OK;
 }
 
@@ -517,20 +535,23 @@ lbm_status lbm_tune(lbm_handle* h, int64_t probe_steps, double* d_scratch, size_
   float best_win_t = 1e30f;
   bool good = true;
   h->variant = 0;
-  for (int wv : wcand) {
-    if (wv != 4 && has_walls(&h->p)) continue;
-    int last_rows = -1;
-    for (int r : cand) {
-      const MarchGeom g = march_geom(h->p.nx, h->p.ny, TileShape{r, wv});
-      if (g.rows == last_rows) continue;  // same tiling as a smaller candidate
-      last_rows = g.rows;
-      h->tile = TileShape{g.rows, wv};
-      float ms = 0;
-      if (!(good = time_it(ms))) break;
-      if (ms < best_t) {
-        best_t = ms;
-        best = h->tile;
+  for (int nt : {1, 0}) {
+    for (int wv : wcand) {
+      if (wv != 4 && has_walls(&h->p)) continue;
+      int last_rows = -1;
+      for (int r : cand) {
+        const MarchGeom g = march_geom(h->p.nx, h->p.ny, TileShape{r, wv, nt});
+        if (g.rows == last_rows) continue;  // same tiling as a smaller candidate
+        last_rows = g.rows;
+        h->tile = TileShape{g.rows, wv, nt};
+        float ms = 0;
+        if (!(good = time_it(ms))) break;
+        if (ms < best_t) {
+          best_t = ms;
+          best = h->tile;
+        }
       }
+      if (!good) break;
     }
     if (!good) break;
   }

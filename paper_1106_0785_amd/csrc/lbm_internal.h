@@ -27,6 +27,7 @@ void make_coef(const lbm_params* p, Hot* c, Cold* cold);
 struct TileShape {
   int rows;
   int waves;
+  int nt = 1;  // 1: non-temporal stores; 0: ordinary stores
 };
 MarchGeom march_geom(int nx, int ny, TileShape t);
 bool has_walls(const lbm_params* p);

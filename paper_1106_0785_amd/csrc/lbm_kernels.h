@@ -300,7 +300,10 @@ __device__ __forceinline__ int xcd_tile(int b, const MarchGeom& g) { return (b %
 // One tile (index `tile` < g.ntiles) of one problem, computed by a workgroup
 // of W wavefronts (2 or 4); HR stencil radius (1: Lax-Wendroff, 2:
 // flux-limited); the ring holds RING = W + 2 HR rows.
-template <int VER, bool WALLS, int W, int HR>
+// NT: non-temporal stores (the new distributions are not kept in the caches;
+// the better choice when the two buffers exceed the caches), else ordinary
+// stores (a grid that fits the caches reads them back from there next step).
+template <int VER, bool WALLS, int W, int HR, bool NT = true>
 __device__ __forceinline__ void fused_tile(Field F, const Hot* __restrict__ hot, const Cold* __restrict__ cold,
                                            MarchGeom g, int tile, int* flag) {
   constexpr int WAVES = W;
@@ -452,7 +455,10 @@ __device__ __forceinline__ void fused_tile(Field F, const Hot* __restrict__ hot,
         nv.ux_ym = ring[sm][16][c0];
         nv.uy_ym = ring[sm][17][c0];
         ok &= collide_add<VER>(c, f, nv, out) || x >= F.nx;
-        store_node_stream(F, x, y, out);
+        if constexpr (NT)
+          store_node_stream(F, x, y, out);
+        else
+          store_node(F, x, y, out);
         if (WALLS) walls_from<VER>(F, c, cold, x, y, out);
       }
     }
@@ -478,12 +484,12 @@ __device__ __forceinline__ void fused_tile(Field F, const Hot* __restrict__ hot,
   if (!ok) flag[0] = 1;
 }
 
-template <int VER, bool WALLS, int W, int HR>
+template <int VER, bool WALLS, int W, int HR, bool NT>
 __global__ __launch_bounds__(64 * W, 2) void k_step_fused(Field F, const Hot* __restrict__ hot,
                                                            const Cold* __restrict__ cold, MarchGeom g, int* flag) {
   const int tile = xcd_tile(blockIdx.x, g);
   if (tile >= g.ntiles) return;  // whole workgroup leaves together
-  fused_tile<VER, WALLS, W, HR>(F, hot, cold, g, tile, flag);
+  fused_tile<VER, WALLS, W, HR, NT>(F, hot, cold, g, tile, flag);
 }
 
 // ---------------------------------------------------------------------------

@@ -85,6 +85,8 @@ def load():
                           ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
             "lbm_get_tile": ([P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
             "lbm_get_variant": ([P, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+            "lbm_set_store_mode": ([P, ctypes.c_int32], ctypes.c_int),
+            "lbm_get_store_mode": ([P, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
             "lbm_set_window": ([P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
             "lbm_get_window": ([P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                 ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
@@ -200,6 +202,16 @@ def lbm_get_variant(h):
     return v.value
 
 
+def lbm_set_store_mode(h, nontemporal):
+    _check(load().lbm_set_store_mode(h, int(nontemporal)))
+
+
+def lbm_get_store_mode(h):
+    v = ctypes.c_int32()
+    _check(load().lbm_get_store_mode(h, ctypes.byref(v)))
+    return v.value
+
+
 def lbm_set_window(h, cols, rows, steps):
     _check(load().lbm_set_window(h, int(cols), int(rows), int(steps)))
 
@@ -292,6 +304,12 @@ class Simulation:
 
     def variant(self):
         return lbm_get_variant(self.handle)
+
+    def set_store_mode(self, nontemporal):
+        lbm_set_store_mode(self.handle, nontemporal)
+
+    def store_mode(self):
+        return lbm_get_store_mode(self.handle)
 
     def set_window(self, cols, rows, steps):
         lbm_set_window(self.handle, cols, rows, steps)

@@ -557,3 +557,35 @@ def test_random_configurations_all_kernels():
         assert_parity(g, o, what="random %d: %dx%d bc (%s, %s) v%d m%d variant %d window %s, %d steps"
                       % (done, nx, ny, bx, by, version, modified, variant, window, steps))
         done += 1
+
+
+@pytest.mark.parametrize("case", ["periodic", "walls", "limited"])
+def test_store_modes_give_identical_results(case):
+    """Non-temporal and ordinary stores in the fused kernel: the same
+    results bit for bit (a cache hint only)."""
+    from paper_1106_0785_amd import lbm
+
+    if case == "periodic":
+        p, fl = _small(16, 300, 100, ["periodic"] * 4)
+    elif case == "walls":
+        p, fl, _ = inputs.couette(0.7, nx=40, ny=64)
+    else:
+        p, fl, _ = inputs.rm(seed=9, nx=200, ny=60, width_cells=0.5)
+        p["scheme"] = 1
+    f = []
+    for nt in (1, 0):
+        sim = lbm.Simulation(p)
+        sim.set_variant(0)
+        sim.set_store_mode(nt)
+        assert sim.store_mode() == nt
+        sim.init(**fl)
+        sim.step(41)
+        f.append(sim.get_f().cpu().numpy())
+        sim.check()
+        sim.close()
+    log("store modes, %s: bitwise equal %s" % (case, np.array_equal(f[0], f[1])))
+    assert np.array_equal(f[0], f[1])
+    sim = lbm.Simulation(p)
+    with pytest.raises(lbm.LbmError):
+        sim.set_store_mode(2)
+    sim.close()
