@@ -158,8 +158,9 @@ lbm_status lbm_set_tile(lbm_handle* h, int32_t rows, int32_t waves);
 /* Stores of the fused kernel (variant 0): nontemporal = 1 marks the new
  * distributions as not to be kept in the caches, 0 uses ordinary stores
  * (better while both distribution buffers fit in the caches, so the next
- * step reads them back from there). Default: 0 when the two buffers take at
- * most 512 MB, else 1; lbm_tune times both. Results do not depend on it. */
+ * step reads them back from there). Default: 0 when the two buffers take
+ * between 32 and 512 MB, else 1; lbm_tune times both. Results do not
+ * depend on it. */
 lbm_status lbm_set_store_mode(lbm_handle* h, int32_t nontemporal);
 lbm_status lbm_get_store_mode(const lbm_handle* h, int32_t* nontemporal);
 

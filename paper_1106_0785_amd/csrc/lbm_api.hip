@@ -262,9 +262,11 @@ TileShape default_tile(int nx, int ny) {
   const long long strips = (nx + STRIP - 1) / STRIP;
   int rows = 64;
   while (rows > WAVES && strips * ((ny + rows - 1) / rows) < 1024) rows /= 2;
-  // ordinary stores while both buffers (256 bytes per node) fit in 512 MB
-  // (measured: faster up to 2048 x 512, slower at 4096 x 1024)
-  const int nt = (long long)nx * ny * 256 > (512ll << 20) ? 1 : 0;
+  // ordinary stores while both buffers (256 bytes per node) take between 32
+  // and 512 MB (measured per step: faster at 1024 x 256 and 2048 x 512,
+  // slower at 512 x 128 and 4096 x 1024)
+  const long long bytes = (long long)nx * ny * 256;
+  const int nt = (bytes > (32ll << 20) && bytes <= (512ll << 20)) ? 0 : 1;
   return TileShape{rows, WAVES, nt};
 }
 
