@@ -339,7 +339,7 @@ def main():
                     "its JSON (for profiling; not the benchmark line)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs on a single MI355X (no multi-GPU path); "
+        print("bench.py measures one GPU: the library runs on a single MI355X (no multi-GPU path); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
