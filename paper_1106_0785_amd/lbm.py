@@ -318,9 +318,12 @@ class Simulation:
         return lbm_get_window(self.handle)
 
     def tune(self, probe_steps=20, keep_state=True):
-        """Pick the fastest tile shape (rows, waves); with keep_state the
-        state is saved to a scratch tensor and restored. Returns (rows,
-        waves, best_ms)."""
+        """Time the fused kernel's tile shapes and store modes and, where it
+        applies, the windowed kernel's window shapes; keep the fastest
+        (variant(), tile(), store_mode(), window() report the choice). With
+        keep_state the state is saved to a scratch tensor and restored.
+        Returns (rows, waves, best_ms) of the fastest fused tile and the best
+        time over all candidates."""
         import torch
 
         scratch = None
