@@ -149,7 +149,8 @@ lbm_status lbm_check(lbm_handle* h);
  * not bound by launch cost. All variants give the same results to rounding.
  * lbm_set_tile sets the tile shape of variant 0:
  * rows per workgroup tile (1..1024, rounded up to a multiple of waves) and
- * wavefronts per workgroup (2 or 4; problems with NEQ walls always use 4).
+ * wavefronts per workgroup (2 or 4; problems with NEQ walls or scheme 1
+ * always use 4).
  * Results do not depend on the tile shape. */
 lbm_status lbm_set_variant(lbm_handle* h, int32_t variant);
 lbm_status lbm_get_variant(const lbm_handle* h, int32_t* variant);

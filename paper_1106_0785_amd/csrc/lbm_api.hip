@@ -461,7 +461,8 @@ lbm_status lbm_set_tile(lbm_handle* h, int32_t rows, int32_t waves) {
   if (!h) return fail(LBM_EINVAL, "handle is NULL");
   if (rows < 1 || rows > 1024) return fail(LBM_EINVAL, "rows must be in 1..1024");
   if (waves != 2 && waves != 4) return fail(LBM_EINVAL, "waves must be 2 or 4");
-  h->tile = TileShape{rows, has_walls(&h->p) ? 4 : waves, h->tile.nt};
+  // NEQ walls and the flux-limited scheme always run 4-wave tiles
+  h->tile = TileShape{rows, (has_walls(&h->p) || h->p.scheme == 1) ? 4 : waves, h->tile.nt};
   return LBM_OK;
 }
 
@@ -539,7 +540,7 @@ lbm_status lbm_tune(lbm_handle* h, int64_t probe_steps, double* d_scratch, size_
   h->variant = 0;
   for (int nt : {1, 0}) {
     for (int wv : wcand) {
-      if (wv != 4 && has_walls(&h->p)) continue;
+      if (wv != 4 && (has_walls(&h->p) || h->p.scheme == 1)) continue;
       int last_rows = -1;
       for (int r : cand) {
         const MarchGeom g = march_geom(h->p.nx, h->p.ny, TileShape{r, wv, nt});
