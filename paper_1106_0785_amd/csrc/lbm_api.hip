@@ -191,9 +191,12 @@ bool window_problem(const lbm_params* p) { return p->scheme == 0 && !small_probl
 bool narrow_problem(const lbm_params* p) { return window_problem(p) && p->ny <= 16; }
 
 // One axis of the window shape: the whole axis in one window when it fits,
-// else windows of w nodes writing w - 2 h each.
-WinAxis win_axis(int len, int w, int h) {
+// else windows of w nodes overlapping by `halo` nodes on each cut side and
+// writing w - 2 halo each. halo = h, or h + 1 on an axis with NEQ walls (a
+// wall node takes its neighbour's value of the same step).
+WinAxis win_axis(int len, int w, int h, bool walls) {
   WinAxis a;
+  a.halo = h + (walls ? 1 : 0);
   if (len <= w) {
     a.w = len;
     a.v = len;
@@ -201,18 +204,20 @@ WinAxis win_axis(int len, int w, int h) {
     a.whole = 1;
   } else {
     a.w = w;
-    a.v = w - 2 * h;
+    a.v = w - 2 * a.halo;
     a.nwin = a.v >= 1 ? (len + a.v - 1) / a.v : 0;  // v < 1: rejected by make_window
     a.whole = 0;
   }
   return a;
 }
 
-// Checks a window shape (wc columns, wr rows, h steps per launch) for an
-// nx-by-ny grid; fills g when it is valid.
-bool make_window(int nx, int ny, int wc, int wr, int h, WinGeom* g) {
+// Checks a window shape (wc columns, wr rows, h steps per launch) for
+// problem p; fills g when it is valid.
+bool make_window(const lbm_params* p, int wc, int wr, int h, WinGeom* g) {
   if (h < 1 || wc < 1 || wr < 1) return false;
-  const WinAxis x = win_axis(nx, wc, h), y = win_axis(ny, wr, h);
+  const bool xw = p->bc[0] == LBM_BC_NEQ_WALL || p->bc[1] == LBM_BC_NEQ_WALL;
+  const bool yw = p->bc[2] == LBM_BC_NEQ_WALL || p->bc[3] == LBM_BC_NEQ_WALL;
+  const WinAxis x = win_axis(p->nx, wc, h, xw), y = win_axis(p->ny, wr, h, yw);
   if (x.v < 1 || y.v < 1) return false;
   if ((long long)x.w * y.w > SMALL_NODES) return false;
   g->x = x;
@@ -223,13 +228,13 @@ bool make_window(int nx, int ny, int wc, int wr, int h, WinGeom* g) {
 
 // Default window shape: narrow grids take every row and 64 columns (32 when
 // ny > 8), h = columns / 8; other grids 32 x 16 nodes, h = 2.
-WinGeom default_window(int nx, int ny) {
+WinGeom default_window(const lbm_params* p) {
   WinGeom g{};
-  if (ny <= 16) {
-    const int wc = ny <= 8 ? 64 : 32;
-    make_window(nx, ny, wc, ny, wc / 8, &g);
+  if (p->ny <= 16) {
+    const int wc = p->ny <= 8 ? 64 : 32;
+    make_window(p, wc, p->ny, wc / 8, &g);
   } else {
-    make_window(nx, ny, 32, 16, 2, &g);
+    make_window(p, 32, 16, 2, &g);
   }
   return g;
 }
@@ -335,7 +340,7 @@ lbm_status lbm_create(const lbm_params* p, void* d_workspace, size_t ws_bytes, v
   h->dev = (Consts*)(base + 2 * 16 * h->plane * sizeof(double) + 256);
   h->cur = 0;
   h->variant = small_problem(p) ? 2 : narrow_problem(p) ? 3 : 0;
-  h->win = default_window(p->nx, p->ny);
+  h->win = default_window(p);
   h->tile = default_tile(p->nx, p->ny);
   e = hipMemsetAsync(h->flag, 0, 256, h->stream);
   if (e == hipSuccess)
@@ -482,7 +487,7 @@ lbm_status lbm_get_store_mode(const lbm_handle* h, int32_t* nontemporal) {
 lbm_status lbm_set_window(lbm_handle* h, int32_t cols, int32_t rows, int32_t steps) {
   if (!h) return fail(LBM_EINVAL, "handle is NULL");
   WinGeom g;
-  if (!make_window(h->p.nx, h->p.ny, cols, rows, steps, &g))
+  if (!make_window(&h->p, cols, rows, steps, &g))
     return fail(LBM_EINVAL,
                 "window %d x %d with %d steps: need steps >= 1, a cut axis longer than 2 steps, "
                 "and at most %d nodes held",
@@ -575,7 +580,7 @@ lbm_status lbm_tune(lbm_handle* h, int64_t probe_steps, double* d_scratch, size_
     h->variant = 3;
     for (int i = 0; i < ns && good; ++i) {
       WinGeom g;
-      if (!make_window(h->p.nx, h->p.ny, shapes[i][0], shapes[i][1], shapes[i][2], &g)) continue;
+      if (!make_window(&h->p, shapes[i][0], shapes[i][1], shapes[i][2], &g)) continue;
       h->win = g;
       float ms = 0;
       if (!(good = time_it(ms))) break;

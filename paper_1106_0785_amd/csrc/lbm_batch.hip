@@ -175,7 +175,16 @@ static lbm_status build_chunks(lbm_batch* b, const Schedule& s) {
         ch.push_back(LineChunk{i, 0, N, 0});
       } else {
         const int C = s.region - 2 * s.h;
-        for (int st = 0; st < N; st += C) ch.push_back(LineChunk{i, st, std::min(C, N - st), 0});
+        // A NEQ wall node takes its fluid neighbour's value of the same step,
+        // so the chunk that writes the last node (a wall when the line has
+        // walls) also writes the node before it: no one-node last chunk.
+        int st = 0;
+        while (st < N) {
+          int len = std::min(C, N - st);
+          if (b->host_insts[i].walls && N - st - len == 1) --len;
+          ch.push_back(LineChunk{i, st, len, 0});
+          st += len;
+        }
       }
     }
     b->vend[ver] = (int)ch.size();

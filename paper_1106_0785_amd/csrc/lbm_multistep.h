@@ -111,9 +111,13 @@ __global__ __launch_bounds__(SMALL_NODES) void k_step_small(Field F, const Hot* 
 // ---------------------------------------------------------------------------
 struct WinAxis {
   int w;      // window extent (nodes held); the whole axis when nwin == 1 and whole
-  int v;      // nodes written per window (w - 2 h on a cut axis)
+  int v;      // nodes written per window (w - 2 halo on a cut axis)
   int nwin;   // windows along the axis
   int whole;  // 1: one window holds the whole axis (no cuts)
+  int halo;   // overlap per cut side: h, or h + 1 on an axis with NEQ walls
+              // (a wall node takes its fluid neighbour's value of the same
+              // step, so it is exact one step less long than its distance
+              // from a cut side)
 };
 
 struct WinGeom {
@@ -128,7 +132,7 @@ struct WinSpan {
   bool lo_cut, hi_cut;
 };
 
-__device__ __forceinline__ WinSpan win_span(const WinAxis& a, int h, int win, int len, bool per) {
+__device__ __forceinline__ WinSpan win_span(const WinAxis& a, int win, int len, bool per) {
   WinSpan r;
   if (a.whole) {
     r.s = 0;
@@ -140,7 +144,7 @@ __device__ __forceinline__ WinSpan win_span(const WinAxis& a, int h, int win, in
   }
   r.o = win * a.v;
   r.v = a.v;
-  int s = r.o - h, e = r.o + a.v + h;
+  int s = r.o - a.halo, e = r.o + a.v + a.halo;
   if (!per) {
     s = max(s, 0);
     e = min(e, len);
@@ -183,8 +187,8 @@ __global__ __launch_bounds__(NODES) void k_step_window(Field F, const Hot* __res
   stage_hot(hot, &hs);
   const Hot& c = hs;
   const bool xper = c.bc[0] == BC_PERIODIC, yper = c.bc[2] == BC_PERIODIC;
-  const WinSpan sx = win_span(wg.x, wg.h, blockIdx.x % wg.x.nwin, F.nx, xper);
-  const WinSpan sy = win_span(wg.y, wg.h, blockIdx.x / wg.x.nwin, F.ny, yper);
+  const WinSpan sx = win_span(wg.x, blockIdx.x % wg.x.nwin, F.nx, xper);
+  const WinSpan sy = win_span(wg.y, blockIdx.x / wg.x.nwin, F.ny, yper);
   const int t = threadIdx.x;
   const bool active = t < sx.n * sy.n;
   const int xw = active ? t % sx.n : 0, yw = active ? t / sx.n : 0;

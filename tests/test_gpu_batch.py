@@ -255,3 +255,32 @@ def test_batch_with_the_flux_limited_scheme():
         assert_parity({k: b.split(v, i) for k, v in m.items()}, o,
                       what="batch instance %d (%s, scheme %d)" % (i, kind, p.get("scheme", 0)))
     b.close()
+
+
+@pytest.mark.parametrize("region,h", [(128, 16), (256, 16), (128, 8)])
+def test_wall_lines_whose_last_chunk_would_be_one_node(region, h):
+    """Couette columns longer than a line region, with lengths N = k C + 1
+    (C = region - 2 h nodes per chunk), so that plain chunking would leave
+    the wall node alone in the last chunk: the chunk that writes the wall
+    also writes its fluid neighbour, whose value the wall takes in the same
+    step. Against the oracle after a number of steps that is not a
+    multiple of h."""
+    from paper_1106_0785_amd.batch import Batch
+
+    C = region - 2 * h
+    items = []
+    for k, pr in ((1, 0.7), (2, 1.5)):
+        p, fl, _ = inputs.couette(pr, nx=1, ny=k * C + 1)
+        items.append((p, fl))
+    p, fl, _ = inputs.riemann("sod", Pr=1.0, nx=k * C + 1, ny=1)
+    items.append((p, fl))
+    b = Batch([p for p, _ in items])
+    b.init([f for _, f in items])
+    b.set_schedule(region, h)
+    steps = 5 * h + 3
+    b.step(steps)
+    b.check()
+    for i, (p, fl) in enumerate(items):
+        o, _ = oracle_run(p, fl, steps)
+        assert_parity(_moments_of(b, i), o, what="wall line %d (N = %d), schedule (%d, %d)" % (i, p["nx"] * p["ny"], region, h))
+    b.close()
