@@ -591,7 +591,7 @@ def test_store_modes_give_identical_results(case):
     sim.close()
 
 
-@pytest.mark.parametrize("case", ["y_walls_23x37", "x_walls_97x3", "x_walls_193x5"])
+@pytest.mark.parametrize("case", ["y_walls_23x37", "x_walls_193x3", "x_walls_193x5"])
 def test_window_kernel_wall_node_written_alone(case):
     """Shapes where a window's written part is (almost) only a wall node:
     the wall takes its fluid neighbour's value of the same step, so cut sides
@@ -601,7 +601,7 @@ def test_window_kernel_wall_node_written_alone(case):
     if case == "y_walls_23x37":
         p, fl = _small(21, 23, 37, ["periodic", "periodic", "neq_wall", "neq_wall"], eq_version=2, modified=0)
     else:
-        nx, ny = (97, 3) if case == "x_walls_97x3" else (193, 5)
+        nx, ny = (193, 3) if case == "x_walls_193x3" else (193, 5)
         p, fl = _small(22, nx, ny, ["neq_wall", "neq_wall", "periodic", "periodic"])
     for side in range(4):
         p["wall"][side] = [1.0, 0.02 * side, -0.01 * side, 1.0 + 0.01 * side]
