@@ -240,3 +240,42 @@ def test_rm_adjoint_finite_differences_and_timing():
         worst = max(worst, rel)
         log("direction %d: adjoint %.10e  central FD %.10e  rel %.2e" % (k, adj, fd, rel))
     assert worst <= 1e-6
+
+
+def test_random_problems_against_complex_step():
+    """20 seeded random problems (shape, boundary kinds including NEQ walls,
+    equilibrium version, modification, rates, step count, checkpoint
+    interval): the adjoint's directional derivative against the oracle's
+    complex step."""
+    rng = np.random.default_rng(404)
+    kinds = ["periodic", "zero_gradient", "specular", "dirichlet_eq", "neq_wall"]
+    done = 0
+    worst = 0.0
+    while done < 20:
+        nx, ny = int(rng.integers(1, 60)), int(rng.integers(1, 40))
+        bx, by = kinds[int(rng.integers(0, 5))], kinds[int(rng.integers(0, 5))]
+        if bx == "neq_wall" and by == "neq_wall":
+            continue
+        if (nx == 1 and bx != "periodic") or (ny == 1 and by != "periodic"):
+            continue
+        if (bx == "neq_wall" and nx < 3) or (by == "neq_wall" and ny < 3):
+            continue
+        p, fl = inputs.smooth_periodic(seed=int(rng.integers(0, 10 ** 6)), nx=nx, ny=ny, amp=0.06,
+                                       eq_version=int(rng.integers(1, 4)), modified=int(rng.integers(0, 3)))
+        p["bc"] = [bx, bx, by, by]
+        for side in range(4):
+            p["wall"][side] = [1.0 + 0.05 * rng.random(), 0.05 * rng.standard_normal(), 0.05 * rng.standard_normal(),
+                               1.0 + 0.05 * rng.random()]
+        p["s"][4], p["s"][5], p["s"][6], p["s"][7] = [float(x) for x in rng.uniform(500, 1900, 4)]
+        steps, ckpt = int(rng.integers(1, 50)), int(rng.integers(0, 9))
+        w_rho, w_T = rng.standard_normal((ny, nx)), rng.standard_normal((ny, nx))
+        d_fields = [rng.standard_normal((ny, nx)) for _ in range(4)]
+        d_logs = rng.standard_normal(16)
+        got, _ = _adjoint_directional(p, fl, steps, w_rho, w_T, d_fields, d_logs, ckpt=ckpt)
+        ref = _complex_step(p, fl, steps, w_rho, w_T, d_fields, d_logs)
+        rel = abs(got - ref) / abs(ref)
+        log("random adjoint %d: %dx%d (%s, %s), %d steps, ckpt %d: rel diff %.2e" % (done, nx, ny, bx, by, steps, ckpt, rel))
+        assert rel <= 1e-9
+        worst = max(worst, rel)
+        done += 1
+    log("random adjoint problems: worst rel diff %.2e" % worst)
