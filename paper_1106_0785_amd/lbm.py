@@ -62,11 +62,18 @@ _lib = None
 
 
 def load():
-    """Load liblbm.so (raises if it has not been built)."""
+    """Load liblbm.so (raises if it has not been built).
+
+    PyTorch is imported first: it brings its own HIP runtime, and the
+    library must bind to that same runtime (loaded before PyTorch, the
+    library would pull in a second runtime, whose streams do not see the
+    device memory PyTorch allocates)."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("liblbm.so is not built: run __graft_entry__.build() (hipcc, gfx950)")
+        import torch  # noqa: F401  (the HIP runtime the library shares)
+
         lib = ctypes.CDLL(LIB_PATH)
         P = ctypes.c_void_p
         pp = ctypes.POINTER(LbmParams)

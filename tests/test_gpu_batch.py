@@ -284,3 +284,76 @@ def test_wall_lines_whose_last_chunk_would_be_one_node(region, h):
         o, _ = oracle_run(p, fl, steps)
         assert_parity(_moments_of(b, i), o, what="wall line %d (N = %d), schedule (%d, %d)" % (i, p["nx"] * p["ny"], region, h))
     b.close()
+
+
+def test_random_batches():
+    """8 seeded random batches: Couette columns and channels (NEQ walls,
+    some longer than a line region), Riemann lines, periodic lines and 2-D
+    states, with a random line schedule, tile height, step count and
+    per-instance budgets; every instance against the oracle."""
+    from paper_1106_0785_amd import lbm
+    from paper_1106_0785_amd.batch import Batch
+
+    rng = np.random.default_rng(99)
+    for trial in range(8):
+        items = []
+        for _ in range(int(rng.integers(2, 9))):
+            kind = int(rng.integers(0, 5))
+            if kind == 0:
+                p, fl, _ = inputs.couette(float(rng.uniform(0.4, 2.5)), nx=1, ny=int(rng.integers(3, 600)))
+            elif kind == 1:
+                p, fl, _ = inputs.couette_x(float(rng.uniform(0.4, 2.5)), nx=int(rng.integers(3, 600)), ny=1)
+            elif kind == 2:
+                p, fl, _ = inputs.riemann("sod", Pr=1.0, nx=int(rng.integers(16, 700)), ny=1)
+            elif kind == 3:
+                p, fl = inputs.smooth_periodic(seed=int(rng.integers(0, 10 ** 6)), nx=int(rng.integers(2, 300)), ny=1,
+                                               amp=0.05)
+            else:
+                p, fl = inputs.smooth_periodic(seed=int(rng.integers(0, 10 ** 6)), nx=int(rng.integers(2, 70)),
+                                               ny=int(rng.integers(3, 40)), amp=0.05, eq_version=int(rng.integers(1, 4)))
+            if lbm.lbm_workspace_bytes(p) > 0:
+                items.append((p, fl))
+        b = Batch([p for p, _ in items])
+        b.init([f for _, f in items])
+        region = int(rng.choice([128, 256]))
+        h = int(rng.choice([4, 8, 16, 32]))
+        b.set_schedule(region, h)
+        b.set_tile_rows(int(rng.choice([4, 16, 64])))
+        steps = int(rng.integers(1, 100))
+        budgets = [int(rng.integers(0, steps + 5)) for _ in items] if rng.random() < 0.5 else None
+        if budgets:
+            b.set_budgets(budgets)
+        b.step(steps)
+        b.check()
+        m = {k: v.cpu().numpy() for k, v in b.moments().items()}
+        for i, (p, fl) in enumerate(items):
+            n = steps if budgets is None else min(steps, budgets[i])
+            o, _ = oracle_run(p, fl, n)
+            assert_parity({k: b.split(v, i) for k, v in m.items()}, o,
+                          what="random batch %d instance %d (%dx%d, %s), schedule (%d, %d), %d steps"
+                          % (trial, i, p["nx"], p["ny"], p["bc"][0], region, h, n))
+        b.close()
+
+
+def test_library_loaded_before_any_tensor():
+    """A process whose first call into the library is a host-only one (the
+    workspace size) and that creates tensors only afterwards: the binding
+    loads PyTorch's HIP runtime before the library, so both share one
+    runtime and the batch runs. Run in a fresh process, where nothing has
+    imported PyTorch yet."""
+    import os
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    script = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "from paper_1106_0785_amd import inputs, lbm\n"
+        "p, fl, _ = inputs.couette(1.0, nx=1, ny=300)\n"
+        "assert lbm.lbm_workspace_bytes(p) > 0\n"
+        "from paper_1106_0785_amd.batch import Batch\n"
+        "b = Batch([p]); b.init([fl]); b.step(10); b.check(); b.close()\n"
+        "print('ok')\n" % root)
+    r = subprocess.run([sys.executable, "-c", script], capture_output=True, text=True, timeout=100)
+    log("fresh process: rc %d, %s" % (r.returncode, (r.stdout + r.stderr).strip()[-300:]))
+    assert r.returncode == 0 and "ok" in r.stdout
