@@ -129,3 +129,36 @@ def test_equal_rates_reduce_to_single_relaxation():
             got = oracle.run(srt, f0, 1)
             err = np.max(np.abs(got - expect)) / np.max(np.abs(f0))
             assert err < 1e-13, (version, modified, err)
+
+
+def test_neq_wall_nodes_carry_wall_velocity_and_temperature():
+    """Sec. IV.A, non-equilibrium extrapolation: a wall node is the
+    equilibrium at (fluid neighbour's density, wall velocity, wall
+    temperature) plus the neighbour's non-equilibrium part f - f^eq(f). That
+    part has no density, momentum or energy, so after every step each wall
+    node's density equals its neighbour's and its velocity and temperature
+    are exactly the wall's (to rounding), for every equilibrium version and
+    modification mode, on walls normal to either axis."""
+    for version in (1, 2, 3):
+        for modified in (0, 1, 2):
+            for axis in ("y", "x"):
+                if axis == "y":
+                    p, fl = inputs.smooth_periodic(seed=40 + version, nx=9, ny=12, amp=0.06, eq_version=version,
+                                                   modified=modified)
+                    p["bc"] = ["periodic", "periodic", "neq_wall", "neq_wall"]
+                else:
+                    p, fl = inputs.smooth_periodic(seed=50 + version, nx=12, ny=9, amp=0.06, eq_version=version,
+                                                   modified=modified)
+                    p["bc"] = ["neq_wall", "neq_wall", "periodic", "periodic"]
+                lo, hi = (2, 3) if axis == "y" else (0, 1)
+                p["wall"][lo] = [1.0, 0.03, -0.02, 0.98]
+                p["wall"][hi] = [1.0, -0.05, 0.04, 1.03]
+                f = oracle.run(p, oracle.init(p, **fl), 7)
+                m = oracle.moments(p, f)
+                for side, idx, nb in ((lo, 0, 1), (hi, -1, -2)):
+                    take = (lambda a, i: a[i, :]) if axis == "y" else (lambda a, i: a[:, i])
+                    _, ux, uy, T = p["wall"][side]
+                    assert np.allclose(take(m["ux"], idx), ux, rtol=0, atol=1e-13)
+                    assert np.allclose(take(m["uy"], idx), uy, rtol=0, atol=1e-13)
+                    assert np.allclose(take(m["T"], idx), T, rtol=1e-13, atol=0)
+                    assert np.allclose(take(m["rho"], idx), take(m["rho"], nb), rtol=1e-13, atol=0)
