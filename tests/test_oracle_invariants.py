@@ -162,3 +162,39 @@ def test_neq_wall_nodes_carry_wall_velocity_and_temperature():
                     assert np.allclose(take(m["uy"], idx), uy, rtol=0, atol=1e-13)
                     assert np.allclose(take(m["T"], idx), T, rtol=1e-13, atol=0)
                     assert np.allclose(take(m["rho"], idx), take(m["rho"], nb), rtol=1e-13, atol=0)
+
+
+def test_uniform_states_are_fixed_points_of_every_boundary_kind():
+    """A uniform equilibrium state is left unchanged (to rounding) by a step
+    with each boundary kind under the conditions where that kind is
+    compatible with it: zero-gradient for any velocity; specular walls when
+    the velocity normal to them is zero; fixed-state ghosts equal to the
+    state; NEQ walls moving with the fluid at its temperature (Sec. IV). A
+    ghost built from the wrong node, a mirror of the wrong planes or a wall
+    state taken from the wrong side moves the state."""
+    rho, ux, uy, T = 1.1, 0.07, -0.04, 0.93
+    cases = [
+        (["zero_gradient"] * 4, (ux, uy)),
+        (["specular", "specular", "periodic", "periodic"], (0.0, uy)),
+        (["periodic", "periodic", "specular", "specular"], (ux, 0.0)),
+        (["dirichlet_eq", "dirichlet_eq", "zero_gradient", "zero_gradient"], (ux, uy)),
+        (["periodic", "periodic", "neq_wall", "neq_wall"], (ux, uy)),
+        (["neq_wall", "neq_wall", "specular", "specular"], (ux, 0.0)),
+    ]
+    for version in (1, 2, 3):
+        for bc, (u, v) in cases:
+            p, _ = inputs.smooth_periodic(seed=1, nx=7, ny=6, eq_version=version)
+            p["bc"] = bc
+            for side in range(4):
+                p["wall"][side] = [rho, u, v, T]
+            fl = {k: np.full((6, 7), val) for k, val in (("rho", rho), ("ux", u), ("uy", v), ("T", T))}
+            f0 = oracle.init(p, **fl)
+            f1 = oracle.run(p, f0, 3)
+            err = float(np.max(np.abs(f1 - f0)) / np.max(np.abs(f0)))
+            assert err < 1e-14, (version, bc, err)
+    # and a specular wall with a normal velocity is not a fixed point
+    p, _ = inputs.smooth_periodic(seed=1, nx=7, ny=6)
+    p["bc"] = ["specular", "specular", "periodic", "periodic"]
+    fl = {k: np.full((6, 7), val) for k, val in (("rho", rho), ("ux", ux), ("uy", uy), ("T", T))}
+    f0 = oracle.init(p, **fl)
+    assert np.max(np.abs(oracle.run(p, f0, 3) - f0)) > 1e-6
