@@ -52,6 +52,13 @@ lbm_status lbm_adjoint_backward(lbm_adjoint* a, const double* d_rho0, const doub
                                 const double* d_g_uy, const double* d_g_T, double* d_grad_rho0,
                                 double* d_grad_ux0, double* d_grad_uy0, double* d_grad_T0, double* d_grad_s);
 
+/* Synchronises the stream and reads the device health flag of every step
+ * the forward and reverse sweeps ran since the last check (the checkpointed
+ * forward steps and the recomputed segments): LBM_OK, or LBM_ENONFINITE if
+ * one of them produced rho <= 0, T <= 0 or a NaN (the gradients of such a
+ * trajectory are meaningless); the flag is then cleared. */
+lbm_status lbm_adjoint_check(lbm_adjoint* a);
+
 void lbm_adjoint_destroy(lbm_adjoint* a);
 
 #ifdef __cplusplus

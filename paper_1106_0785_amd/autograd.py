@@ -27,6 +27,7 @@ def _lib():
             "lbm_adjoint_forward": ([P, P, P, P, P], ctypes.c_int),
             "lbm_adjoint_final_moments": ([P, P, P, P, P, P], ctypes.c_int),
             "lbm_adjoint_backward": ([P] + [P] * 13, ctypes.c_int),
+            "lbm_adjoint_check": ([P], ctypes.c_int),
             "lbm_adjoint_destroy": ([P], None),
         }
         for name, (args, res) in sigs.items():
@@ -74,6 +75,8 @@ class Adjoint:
         out = {k: torch.empty((self.ny, self.nx), dtype=torch.float64, device=self.device)
                for k in ("rho", "ux", "uy", "T", "p")}
         _check(_lib().lbm_adjoint_final_moments(self.handle, *[_p(out[k]) for k in ("rho", "ux", "uy", "T", "p")]))
+        # a trajectory that lost positivity has no meaningful gradient
+        _check(_lib().lbm_adjoint_check(self.handle))
         return out
 
     def backward(self, g_rho=None, g_ux=None, g_uy=None, g_T=None):
@@ -83,6 +86,7 @@ class Adjoint:
         _check(_lib().lbm_adjoint_backward(self.handle, *[_p(t) for t in self._init], *[_p(t) for t in g],
                                            *[_p(t) for t in grads], _p(grad_s)))
         self._keep = g
+        _check(_lib().lbm_adjoint_check(self.handle))
         return grads, grad_s
 
     def close(self):

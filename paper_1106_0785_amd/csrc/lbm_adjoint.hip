@@ -281,6 +281,20 @@ lbm_status lbm_adjoint_backward(lbm_adjoint* a, const double* d_rho0, const doub
   return LBM_OK;
 }
 
+lbm_status lbm_adjoint_check(lbm_adjoint* a) {
+  if (!a) return fail(LBM_EINVAL, "adjoint handle is NULL");
+  int flag = 0;
+  hipError_t e = hipMemcpyAsync(&flag, a->flag(), sizeof(int), hipMemcpyDeviceToHost, a->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(a->stream);
+  if (e != hipSuccess) return hip_fail(e, "reading the health flag");
+  if (flag) {
+    e = hipMemsetAsync(a->flag(), 0, sizeof(int), a->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
+    return fail(LBM_ENONFINITE, "a forward step produced rho <= 0, T <= 0 or NaN");
+  }
+  return LBM_OK;
+}
+
 void lbm_adjoint_destroy(lbm_adjoint* a) { delete a; }
 
 }  // extern "C"

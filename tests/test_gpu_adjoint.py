@@ -279,3 +279,24 @@ def test_random_problems_against_complex_step():
         worst = max(worst, rel)
         done += 1
     log("random adjoint problems: worst rel diff %.2e" % worst)
+
+
+def test_forward_reports_lost_positivity():
+    """A trajectory that loses positivity (here: one node starts at T < 0)
+    raises instead of returning gradients; the handle's flag is cleared, so
+    the next valid run of the same size passes."""
+    import torch
+
+    from paper_1106_0785_amd import lbm
+    from paper_1106_0785_amd.autograd import Adjoint
+
+    p, fl = inputs.smooth_periodic(seed=3, nx=16, ny=8, amp=0.05)
+    bad = {k: v.copy() for k, v in fl.items()}
+    bad["T"][4, 7] = -0.5
+    a = Adjoint(p, 5, 2)
+    with pytest.raises(lbm.LbmError) as err:
+        a.forward(*[torch.from_numpy(bad[k]).cuda() for k in ("rho", "ux", "uy", "T")])
+    assert err.value.status == -5, str(err.value)
+    out = a.forward(*[torch.from_numpy(fl[k]).cuda() for k in ("rho", "ux", "uy", "T")])
+    assert torch.isfinite(out["rho"]).all()
+    a.close()

@@ -5,7 +5,9 @@ tuners), against the oracle:
   * the 4096 x 1024 shock/interface problem (the HBM-resident step), every
     node after a few steps;
   * the 1024 x 256 shock/interface configuration for its full 5000 steps;
-  * the 512-instance uneven batch for 1000 steps, sampled instances;
+  * the same configuration at the fast end of its Mach range (seed 4:
+    Mach 1.95, four interface modes) for its full 5000 steps;
+  * the 512-instance uneven batch for 1000 steps, every instance;
   * the adjoint of 2000 steps at 512 x 128, against the oracle's complex-step
     directional derivative (exact up to rounding).
 """
@@ -51,7 +53,30 @@ def test_rm_1024x256_full_run():
     assert_parity(g, o, what="rm 1024x256 5000 steps")
 
 
-def test_batch_512_sampled_instances():
+def test_rm_1024x256_fast_shock_full_run():
+    p, fl, meta = inputs.rm(seed=4, nx=1024, ny=256)
+    assert meta["mach"] > 1.9 and meta["K"] == 4
+    g, shape = _tuned_run(p, fl, 5000)
+    o, _ = oracle_run(p, fl, 5000)
+    log("1024x256 Mach %.3f, %d modes, tuned %s %s, 5000 steps" % (meta["mach"], meta["K"], shape[0], shape[1]))
+    assert_parity(g, o, what="rm 1024x256 seed 4 5000 steps")
+
+
+def _oracle_instances(items, steps):
+    """Oracle results of every instance, one thread each, instances in
+    parallel (the oracle's foreign calls release the interpreter lock)."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+
+    def one(item):
+        _, p, fl = item
+        return oracle.moments(p, oracle.run(p, oracle.init(p, **fl), steps, nthreads=1))
+
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        return list(ex.map(one, items))
+
+
+def test_batch_512_every_instance():
     from paper_1106_0785_amd.batch import Batch
 
     items = inputs.batch(seed=0, n=512)
@@ -61,14 +86,12 @@ def test_batch_512_sampled_instances():
     b.step(1000)
     b.check()
     m = {k: v.cpu().numpy() for k, v in b.moments().items()}
-    rng = np.random.default_rng(12)
-    picks = sorted(set(int(i) for i in rng.integers(0, 512, size=12)) | {0, 511})
-    for i in picks:
-        kind, p, fl = items[i]
-        o, _ = oracle_run(p, fl, 1000)
-        assert_parity({k: b.split(v, i) for k, v in m.items()}, o,
-                      what="batch512 instance %d (%s, %dx%d), schedule %s" % (i, kind, p["nx"], p["ny"], sched))
+    b_split = [{k: b.split(v, i) for k, v in m.items()} for i in range(len(items))]
     b.close()
+    log("batch512: 1000 steps, schedule %s; oracle on every instance" % (sched,))
+    refs = _oracle_instances(items, 1000)
+    for i, ((kind, p, _), o) in enumerate(zip(items, refs)):
+        assert_parity(b_split[i], o, what="batch512 instance %d (%s, %dx%d)" % (i, kind, p["nx"], p["ny"]))
 
 
 def test_adjoint_512x128_2000_steps_against_complex_step():
