@@ -200,6 +200,31 @@ lbm_status lbm_get_tile(const lbm_handle* h, int32_t* rows, int32_t* waves);
  * Both buffers hold 16 ny pitch doubles and must not overlap. */
 lbm_status lbm_stream_copy(const double* d_src, double* d_dst, int32_t nx, int32_t ny, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * time stepping as lbm_create + lbm_set_f + lbm_step(nsteps) + lbm_get_f,
+ * with the kernel and tile shape lbm_create picks by default, but with no
+ * workspace argument and no allocation of any kind. The two pitched
+ * distribution buffers, the coefficients and the health flag live in one
+ * fixed device array of the library (64 MiB + 64.25 KiB, held on every device
+ * the call runs on until the process ends), so the grid may take at most
+ * LBM_NOALLOC_MAX_NODES stored nodes, counting rows padded to a multiple of
+ * 64 (e.g. 1024 x 256); larger grids are rejected with LBM_EINVAL before
+ * anything is enqueued.
+ *   d_f_in   device [16][ny][nx] distributions of the initial state (read)
+ *   d_f_out  device [16][ny][nx], the state after nsteps >= 0 steps (may be
+ *            d_f_in: the input is copied into the array before any step)
+ *   d_status device int32 or NULL: receives LBM_OK, or LBM_ENONFINITE if a
+ *            step produced rho <= 0, T <= 0 or NaN
+ * Enqueued on hip_stream; nothing is synchronised. Every call on one device
+ * shares that device's array and overwrites it (the coefficients and the
+ * flag are rewritten by each call), so calls whose work overlaps on one
+ * device - other streams, other host threads - race and must be serialised
+ * by the caller. Same validation as lbm_create. */
+#define LBM_NOALLOC_MAX_NODES 262144
+lbm_status lbm_run_noalloc(const lbm_params* p, const double* d_f_in, double* d_f_out, int64_t nsteps,
+                           int32_t* d_status, void* hip_stream);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* lbm_last_error(void);
 

@@ -1,17 +1,20 @@
 """Build liblbm.so (HIP, gfx950) in-tree with hipcc.
 
 The constants header is regenerated from the velocity set and polynomial
-basis first (gen_consts.py checks the factorisation exactly)."""
+basis first (gen_consts.py checks the factorisation exactly). Each source is
+compiled to an object in parallel (objects under _build/), then linked."""
 
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = ["lbm_api.hip", "lbm_batch.hip", "lbm_adjoint.hip", "lbm_stability.hip"]
+OBJ = os.path.join(ROOT, "_build", "obj")
+SOURCES = ["lbm_api.hip", "lbm_batch.hip", "lbm_adjoint.hip", "lbm_stability.hip", "lbm_noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -19,7 +22,6 @@ FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"),
 ]
@@ -31,8 +33,20 @@ def sources():
 
 def build(verbose=False, extra=()):
     subprocess.check_call([sys.executable, os.path.join(CSRC, "gen_consts.py")])
+    os.makedirs(OBJ, exist_ok=True)
+
+    def compile_one(src):
+        obj = os.path.join(OBJ, os.path.basename(src) + ".o")
+        cmd = [HIPCC] + FLAGS + list(extra) + ["-c", src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+        return obj
+
+    with ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 1)) as ex:
+        objs = list(ex.map(compile_one, sources()))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC] + FLAGS + list(extra) + sources() + ["-o", tmp]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

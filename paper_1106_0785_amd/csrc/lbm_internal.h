@@ -6,6 +6,7 @@
 
 #include "../../include/lbm.h"
 #include "lbm_kernels.h"
+#include "lbm_multistep.h"
 
 namespace lbm {
 
@@ -34,5 +35,14 @@ bool has_walls(const lbm_params* p);
 hipError_t launch_step(const Field& F, const Hot* c, const Cold* cold, int version, bool walls, int scheme,
                        int variant, TileShape t, int* flag, hipStream_t s);
 TileShape default_tile(int nx, int ny);
+// Small-grid and windowed kernels (lbm_multistep.h) and their selection
+// rules, as lbm_create applies them.
+bool small_problem(const lbm_params* p);
+bool narrow_problem(const lbm_params* p);
+WinGeom default_window(const lbm_params* p);
+hipError_t launch_small(const Field& F, const Hot* c, const Cold* cold, int version, bool walls, int nsteps,
+                        int* flag, hipStream_t s);
+hipError_t launch_window(const Field& F, const Hot* c, const Cold* cold, int version, bool walls,
+                         const WinGeom& g, int nsteps, int* flag, hipStream_t s);
 
 }  // namespace lbm
