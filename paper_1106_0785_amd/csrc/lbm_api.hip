@@ -166,6 +166,48 @@ hipError_t launch_step(const Field& F, const Hot* c, const Cold* cold, int versi
   return hipGetLastError();
 }
 
+bool two_step_problem(const lbm_params* p) { return p->scheme == 0 && !has_walls(p); }
+
+March2Geom march2_geom(int nx, int ny, TileShape t) {
+  March2Geom g;
+  const int w = t.waves;
+  g.nstrips = (nx + OSTRIP - 1) / OSTRIP;
+  int rows = std::max(w, std::min(t.rows, (ny + w - 1) / w * w));
+  g.rows = (rows + w - 1) / w * w;
+  g.nsegs = (ny + g.rows - 1) / g.rows;
+  g.ntiles = g.nstrips * g.nsegs;
+  g.per_xcd = (g.ntiles + 7) / 8;
+  return g;
+}
+
+hipError_t launch_step2(const Field& F, const Hot* c, const Cold* cold, int version, TileShape t, int* flag,
+                        hipStream_t s) {
+  if (t.waves != 2) t.waves = 4;
+  const March2Geom g = march2_geom(F.nx, F.ny, t);
+  decltype(&k_step_fused2<1, 4, true>) k;
+#define LBM_FUSED2(W)                                                                                    \
+  k = t.nt ? (version == 2 ? k_step_fused2<2, W, true> : version == 3 ? k_step_fused2<3, W, true>        \
+                                                                      : k_step_fused2<1, W, true>)        \
+           : (version == 2 ? k_step_fused2<2, W, false> : version == 3 ? k_step_fused2<3, W, false>      \
+                                                                       : k_step_fused2<1, W, false>)
+  if (t.waves == 2)
+    LBM_FUSED2(2);
+  else
+    LBM_FUSED2(4);
+#undef LBM_FUSED2
+  hipLaunchKernelGGL(k, dim3(8 * g.per_xcd), dim3(64 * t.waves), 0, s, F, c, cold, g, flag);
+  return hipGetLastError();
+}
+
+TileShape default_tile2(int nx, int ny) {
+  const long long strips = (nx + OSTRIP - 1) / OSTRIP;
+  int rows = 64;
+  while (rows > 8 && strips * ((ny + rows - 1) / rows) < 1024) rows /= 2;
+  const long long bytes = (long long)nx * ny * 256;
+  const int nt = (bytes > (32ll << 20) && bytes <= (512ll << 20)) ? 0 : 1;
+  return TileShape{rows, 4, nt};
+}
+
 // True when the whole grid fits the one-workgroup multi-step kernel.
 bool small_problem(const lbm_params* p) {
   return p->scheme == 0 && (long long)p->nx * p->ny <= SMALL_NODES;
@@ -289,6 +331,7 @@ struct lbm_handle {
   long long pitch, plane;
   int variant;
   TileShape tile;
+  TileShape tile2;  // tile shape of variant 4 (two steps per launch)
   WinGeom win;  // window shape of variant 3
 };
 
@@ -342,6 +385,7 @@ lbm_status lbm_create(const lbm_params* p, void* d_workspace, size_t ws_bytes, v
   h->variant = small_problem(p) ? 2 : narrow_problem(p) ? 3 : 0;
   h->win = default_window(p);
   h->tile = default_tile(p->nx, p->ny);
+  h->tile2 = default_tile2(p->nx, p->ny);
   e = hipMemsetAsync(h->flag, 0, 256, h->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(h->dev, &h->host, sizeof(Consts), hipMemcpyHostToDevice, h->stream);
@@ -398,10 +442,20 @@ lbm_status lbm_step(lbm_handle* h, int64_t nsteps) {
     }
     return LBM_OK;
   }
-  for (int64_t n = 0; n < nsteps; ++n) {
+  int64_t n = 0;
+  if (h->variant == 4) {
+    // two steps per launch; an odd last step takes the one-step kernel
+    for (; n + 2 <= nsteps; n += 2) {
+      hipError_t e = launch_step2(field_of(h, h->cur), &h->dev->hot, &h->dev->cold, h->p.eq_version, h->tile2,
+                                  h->flag, h->stream);
+      if (e != hipSuccess) return hip_fail(e, "two-step kernel launch");
+      h->cur ^= 1;
+    }
+  }
+  for (; n < nsteps; ++n) {
     hipError_t e =
         launch_step(field_of(h, h->cur), &h->dev->hot, &h->dev->cold, h->p.eq_version, has_walls(&h->p),
-                    h->p.scheme, h->variant, h->tile, h->flag, h->stream);
+                    h->p.scheme, h->variant == 4 ? 0 : h->variant, h->tile, h->flag, h->stream);
     if (e != hipSuccess) return hip_fail(e, "step kernel launch");
     h->cur ^= 1;
   }
@@ -453,7 +507,9 @@ lbm_status lbm_check(lbm_handle* h) {
 
 lbm_status lbm_set_variant(lbm_handle* h, int32_t variant) {
   if (!h) return fail(LBM_EINVAL, "handle is NULL");
-  if (variant < 0 || variant > 3) return fail(LBM_EINVAL, "variant must be 0, 1, 2 or 3");
+  if (variant < 0 || variant > 4) return fail(LBM_EINVAL, "variant must be 0, 1, 2, 3 or 4");
+  if (variant == 4 && !two_step_problem(&h->p))
+    return fail(LBM_EINVAL, "variant 4 needs scheme 0 and no NEQ walls");
   if (variant == 2 && !small_problem(&h->p))
     return fail(LBM_EINVAL, "variant 2 needs scheme 0 and nx ny <= %d nodes", SMALL_NODES);
   if (variant == 3 && !window_problem(&h->p))
@@ -466,6 +522,10 @@ lbm_status lbm_set_tile(lbm_handle* h, int32_t rows, int32_t waves) {
   if (!h) return fail(LBM_EINVAL, "handle is NULL");
   if (rows < 1 || rows > 1024) return fail(LBM_EINVAL, "rows must be in 1..1024");
   if (waves != 2 && waves != 4) return fail(LBM_EINVAL, "waves must be 2 or 4");
+  if (h->variant == 4) {
+    h->tile2 = TileShape{rows, waves, h->tile2.nt};
+    return LBM_OK;
+  }
   // NEQ walls and the flux-limited scheme always run 4-wave tiles
   h->tile = TileShape{rows, (has_walls(&h->p) || h->p.scheme == 1) ? 4 : waves, h->tile.nt};
   return LBM_OK;
@@ -475,6 +535,7 @@ lbm_status lbm_set_store_mode(lbm_handle* h, int32_t nontemporal) {
   if (!h) return fail(LBM_EINVAL, "handle is NULL");
   if (nontemporal != 0 && nontemporal != 1) return fail(LBM_EINVAL, "nontemporal must be 0 or 1");
   h->tile.nt = nontemporal;
+  h->tile2.nt = nontemporal;
   return LBM_OK;
 }
 
@@ -619,8 +680,9 @@ lbm_status lbm_get_variant(const lbm_handle* h, int32_t* variant) {
 
 lbm_status lbm_get_tile(const lbm_handle* h, int32_t* rows, int32_t* waves) {
   if (!h) return fail(LBM_EINVAL, "handle is NULL");
-  if (rows) *rows = h->tile.rows;
-  if (waves) *waves = h->tile.waves;
+  const TileShape& t = h->variant == 4 ? h->tile2 : h->tile;
+  if (rows) *rows = t.rows;
+  if (waves) *waves = t.waves;
   return LBM_OK;
 }
 

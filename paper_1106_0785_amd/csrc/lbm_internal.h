@@ -7,6 +7,7 @@
 #include "../../include/lbm.h"
 #include "lbm_kernels.h"
 #include "lbm_multistep.h"
+#include "lbm_fused2.h"
 
 namespace lbm {
 
@@ -35,6 +36,12 @@ bool has_walls(const lbm_params* p);
 hipError_t launch_step(const Field& F, const Hot* c, const Cold* cold, int version, bool walls, int scheme,
                        int variant, TileShape t, int* flag, hipStream_t s);
 TileShape default_tile(int nx, int ny);
+// Two steps per launch (lbm_fused2.h): scheme 0 without NEQ walls.
+bool two_step_problem(const lbm_params* p);
+March2Geom march2_geom(int nx, int ny, TileShape t);
+hipError_t launch_step2(const Field& F, const Hot* c, const Cold* cold, int version, TileShape t, int* flag,
+                        hipStream_t s);
+TileShape default_tile2(int nx, int ny);
 // Small-grid and windowed kernels (lbm_multistep.h) and their selection
 // rules, as lbm_create applies them.
 bool small_problem(const lbm_params* p);
