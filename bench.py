@@ -28,7 +28,8 @@ HBM_PEAK = 8.0e12  # bytes/s, MI355X HBM3E
 BYTES_PER_NODE = 256  # 16 FP64 reads + 16 FP64 writes per node update
 ADJ_BYTES_PER_NODE = 384  # adjoint step: lambda^{n+1} and f^n read, lambda^n written (16 FP64 each)
 KERNEL_SOURCES = ["paper_1106_0785_amd/csrc/lbm_kernels.h", "paper_1106_0785_amd/csrc/lbm_step.h",
-                  "paper_1106_0785_amd/csrc/lbm_node.h", "paper_1106_0785_amd/csrc/lbm_consts.h"]
+                  "paper_1106_0785_amd/csrc/lbm_node.h", "paper_1106_0785_amd/csrc/lbm_consts.h",
+                  "paper_1106_0785_amd/csrc/lbm_fused2.h"]
 
 
 def kernel_hash():
@@ -57,7 +58,7 @@ def time_steps(sim, steps, warmup):
     return start.elapsed_time(stop) / 1e3  # seconds
 
 
-VARIANT_KERNELS = {0: "k_step_fused", 1: "k_step_plain", 2: "k_step_small", 3: "k_step_window"}
+VARIANT_KERNELS = {0: "k_step_fused", 1: "k_step_plain", 2: "k_step_small", 3: "k_step_window", 4: "k_step_fused2"}
 
 
 def run_problem(p, fields, steps, warmup, rows=None, tune=False):
@@ -76,6 +77,8 @@ def run_problem(p, fields, steps, warmup, rows=None, tune=False):
     variant = sim.variant()
     window = sim.window() if variant == 3 else None
     stores = "nontemporal" if sim.store_mode() else "ordinary"
+    if tuned and variant == 4:
+        tuned = sim.tile()
     sim.close()
     out = {"seconds": t, "steps": steps, "nodes": nodes, "mlups": nodes * steps / t / 1e6,
            "ms_per_step": 1e3 * t / steps, "gbps": nodes * steps * BYTES_PER_NODE / t / 1e9,
@@ -84,8 +87,10 @@ def run_problem(p, fields, steps, warmup, rows=None, tune=False):
         out["window_cols"], out["window_rows"], out["window_steps"] = window
     elif tuned:
         out["tile_rows"], out["tile_waves"] = tuned[0], tuned[1]
-    if variant == 0:
+    if variant in (0, 4):
         out["stores"] = stores
+    if variant == 4:
+        out["steps_per_launch"] = 2
     return out
 
 
@@ -134,7 +139,6 @@ def bench_batch(steps, seed=0, n=512, plain=True, two_d=False):
 
     out = {"instances": n, "nodes": nodes, "steps": steps, "batched_seconds": tb,
            "batched_mlups": nodes * steps / tb / 1e6,
-           "batched_gbps_equivalent": nodes * steps / tb * BYTES_PER_NODE / 1e9,
            "budgets_seconds": tbb, "budgets_node_steps": budget_node_steps,
            "budgets_mlups": budget_node_steps / tbb / 1e6,
            "schedule": {k: sched[k] for k in ("region", "steps_per_launch", "chunks", "tile_rows", "tiles")}}
@@ -292,40 +296,87 @@ def copy_ceiling(nx, ny, reps=20):
     return out
 
 
-def cpu_baseline(budget_s=15.0):
-    """The oracle as it stands, on the host cores, on a bounded sample of the
-    1024 x 256 shock/interface problem."""
+def _median_rate(fn, work, reps=3):
+    """Median rate (work / s) of `reps` timed calls of fn after one warm-up."""
+    fn()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t0)
+    return work / sorted(ts)[len(ts) // 2]
+
+
+def cpu_baseline():
+    """The oracle, built -O3 -march=native on this host (the same source as
+    the -O2 parity build), timed on samples of the five workloads, on every
+    host thread and on one thread, median of three runs after a warm-up:
+    thermal Couette 4 x 64 (2000 steps), Sod 2000 x 4 (200 steps), the
+    1024 x 256 shock/interface problem (8 steps), 16 instances of the uneven
+    batch (100 steps; instances run side by side on the threads), and the
+    complex-step run that checks the adjoint (512 x 128, 4 steps in complex
+    arithmetic). Rates are node updates per second (MLUPS). value: the
+    1024 x 256 sample on every thread."""
+    from concurrent.futures import ThreadPoolExecutor
+
     import oracle
     from paper_1106_0785_amd import inputs
 
-    p, fl, _ = inputs.rm(seed=0, nx=1024, ny=256)
-    f = oracle.init(p, **fl)
     nt = oracle.max_threads()
-    f = oracle.run(p, f, 1, nthreads=nt)  # warm-up (thread pool start)
-    t0 = time.perf_counter()
-    f = oracle.run(p, f, 2, nthreads=nt)
-    one = (time.perf_counter() - t0) / 2
-    n = max(1, int(budget_s / max(one, 1e-6)))
-    t0 = time.perf_counter()
-    oracle.run(p, f, n, nthreads=nt)
-    t = time.perf_counter() - t0
-    # the same oracle on one thread, a shorter sample
-    t1 = time.perf_counter()
-    n1 = 0
-    while time.perf_counter() - t1 < budget_s / 4:
-        f = oracle.run(p, f, 1, nthreads=1)
-        n1 += 1
-    t1 = time.perf_counter() - t1
+    cfg = {}
+
+    def plain(name, p, fl, steps, sample):
+        f0 = oracle.init(p, **fl)
+        work = p["nx"] * p["ny"] * steps / 1e6
+        r_all = _median_rate(lambda: oracle.run(p, f0, steps, nthreads=nt, variant="native"), work)
+        r_one = _median_rate(lambda: oracle.run(p, f0, steps, nthreads=1, variant="native"), work)
+        cfg[name] = {"mlups_all_threads": r_all, "mlups_1_thread": r_one, "sample": sample}
+
+    pc, flc, _ = inputs.couette(1.0)
+    plain("couette_4x64", pc, flc, 2000, "4x64 thermal Couette, 2000 steps")
+    pr, flr, _ = inputs.riemann("sod", nx=2000, ny=4)
+    plain("riemann_2000x4", pr, flr, 200, "2000x4 Sod tube, 200 steps")
+    p3, fl3, _ = inputs.rm(seed=0, nx=1024, ny=256)
+    plain("rm_1024x256", p3, fl3, 8, "1024x256 shock/interface problem, 8 steps")
+
+    items = inputs.batch(seed=0, n=512)[::32]
+    f0s = [oracle.init(p, **fl) for _, p, fl in items]
+    work = sum(p["nx"] * p["ny"] for _, p, _ in items) * 100 / 1e6
+
+    def batch(threads):
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            list(ex.map(lambda pf: oracle.run(pf[0], pf[1], 100, nthreads=1, variant="native"),
+                        [(p, f) for (_, p, _), f in zip(items, f0s)]))
+
+    cfg["batch_512"] = {"mlups_all_threads": _median_rate(lambda: batch(nt), work),
+                        "mlups_1_thread": _median_rate(lambda: batch(1), work),
+                        "sample": "16 of the 512 instances (every 32nd), 100 steps each"}
+
+    p5, fl5, _ = inputs.rm(seed=0, nx=512, ny=128)
+    rng = np.random.default_rng(21)
+    h = 1e-30
+    cf = {k: fl5[k] + 1j * h * rng.standard_normal(fl5[k].shape) for k in ("rho", "ux", "uy", "T")}
+    fc = oracle.init_complex(p5, cf["rho"], cf["ux"], cf["uy"], cf["T"])
+    s_im = h * np.array(p5["s"]) * rng.standard_normal(16)
+    work = 512 * 128 * 4 / 1e6
+    cfg["adjoint_check_512x128"] = {
+        "mlups_all_threads": _median_rate(lambda: oracle.run_complex(p5, fc, 4, s_im=s_im, nthreads=nt,
+                                                                     variant="native"), work),
+        "mlups_1_thread": _median_rate(lambda: oracle.run_complex(p5, fc, 4, s_im=s_im, nthreads=1,
+                                                                  variant="native"), work),
+        "sample": "512x128 shock/interface problem, 4 steps in complex arithmetic (one directional derivative)"}
     model = ""
     try:
         with open("/proc/cpuinfo") as fh:
             model = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
     except OSError:
         pass
-    return {"value": 1024 * 256 * n / t / 1e6, "unit": "MLUPS", "cores": nt, "kind": "oracle",
-            "sample": "1024x256 shock/interface problem, %d time steps after 3 warm-up steps (%.1f s)" % (n, t),
-            "value_1_thread": 1024 * 256 * n1 / t1 / 1e6, "sample_1_thread": "%d time steps (%.1f s)" % (n1, t1),
-            "cpu_model": model, "logical_cpus": os.cpu_count()}
+    head = cfg["rm_1024x256"]
+    return {"value": head["mlups_all_threads"], "unit": "MLUPS", "cores": nt, "kind": "oracle",
+            "sample": "1024x256 shock/interface problem, 8 time steps, median of 3 runs, all threads",
+            "build": "g++ -O3 -march=native -fopenmp (same source as the -O2 parity build)",
+            "value_1_thread": head["mlups_1_thread"], "configs": cfg, "cpu_model": model,
+            "logical_cpus": os.cpu_count()}
 
 
 def main():
@@ -411,13 +462,20 @@ def main():
 
     log("copy ceiling")
     extra["copy_ceiling_%dx%d" % (nx, ny)] = copy_ceiling(nx, ny)
-    kernel = head["kernel"]  # the tuner keeps the fused kernel at this size (one launch per step)
+    kernel = head["kernel"]  # the kernel the tuner kept at this size
     workload = "rm_%dx%d" % (nx, ny)
-    bytes_per_launch = BYTES_PER_NODE * nx * ny
-    achieved = bytes_per_launch / (head["seconds"] / head["steps"]) / 1e9
+    # algorithmic bytes: 256 per node-step times the node-steps of one launch
+    # (one step per launch, or two for the two-step kernel); the launch time
+    # is the timed region over its launches (an even step count is all
+    # two-step launches)
+    spl = head.get("steps_per_launch", 1)
+    bytes_per_launch = BYTES_PER_NODE * nx * ny * spl
+    launch_s = head["seconds"] / (head["steps"] / spl)
+    achieved = bytes_per_launch / launch_s / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                 "frac": round(achieved * 1e9 / HBM_PEAK, 4), "traffic": traffic_from_profiles(kernel, workload),
-                "kernel": kernel, "algorithmic_bytes_per_launch": bytes_per_launch,
+                "kernel": kernel, "steps_per_launch": spl, "launch_us": round(launch_s * 1e6, 1),
+                "algorithmic_bytes_per_launch": bytes_per_launch,
                 "tile_rows": head.get("tile_rows"), "tile_waves": head.get("tile_waves"), "stores": head.get("stores")}
     out = {
         "metric": "MLUPS (FP64 node updates/s) and fraction of HBM roofline",

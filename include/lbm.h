@@ -144,13 +144,18 @@ lbm_status lbm_check(lbm_handle* h);
  *   3 the windowed kernel (scheme 0 and nx ny > 512, LBM_EINVAL otherwise;
  *     default when ny <= 16): workgroups hold overlapping windows of the grid
  *     in LDS (lbm_set_window) and take several steps per launch,
- *     recomputing the overlap.
+ *     recomputing the overlap;
+ *   4 the fused kernel taking two time steps per launch (scheme 0 without
+ *     NEQ walls, LBM_EINVAL otherwise; default when the two distribution
+ *     buffers take more than 512 MB): the intermediate level stays in LDS,
+ *     so each node's distributions cross HBM once per two steps; an odd
+ *     last step of a call takes variant 0.
  * Variants 2 and 3 take many steps per launch, so small and narrow grids are
  * not bound by launch cost. All variants give the same results to rounding.
- * lbm_set_tile sets the tile shape of variant 0:
- * rows per workgroup tile (1..1024, rounded up to a multiple of waves) and
- * wavefronts per workgroup (2 or 4; problems with NEQ walls or scheme 1
- * always use 4).
+ * lbm_set_tile sets the tile shape of the current variant (0, or 4 for the
+ * two-step kernel, whose shape is kept separately): rows per workgroup tile
+ * (1..1024, rounded up to a multiple of waves) and wavefronts per workgroup
+ * (2 or 4; variant 0 with NEQ walls or scheme 1 always uses 4).
  * Results do not depend on the tile shape. */
 lbm_status lbm_set_variant(lbm_handle* h, int32_t variant);
 lbm_status lbm_get_variant(const lbm_handle* h, int32_t* variant);
@@ -178,18 +183,21 @@ lbm_status lbm_get_window(const lbm_handle* h, int32_t* cols, int32_t* rows, int
 
 /* Tuner: times probe_steps steps for each candidate fused tile shape
  * (wavefronts per workgroup x tile height x store mode) and keeps the
- * fastest. When the
- * handle uses variant 0 or 3 and the windowed kernel applies, it also times
- * window shapes (every row for grids of <= 16 rows, two-dimensional windows
- * otherwise) and then uses whichever kernel and shape was fastest
- * (lbm_get_variant, lbm_get_window). Variants 1 and 2 are kept. Synchronises
- * the stream. rows_out, waves_out: the fastest fused tile; best_ms: the best
+ * fastest. When the handle uses variant 0, 3 or 4, it also times the
+ * two-step kernel's tile shapes where that kernel applies (over probe_steps
+ * rounded up to even) and window shapes where the windowed kernel applies
+ * (every row for grids of <= 16 rows, two-dimensional windows otherwise),
+ * and then uses whichever kernel and shape was fastest (lbm_get_variant,
+ * lbm_get_tile, lbm_get_window). Variants 1 and 2 are kept. Synchronises
+ * the stream. rows_out, waves_out: the tile shape of the kernel kept (the
+ * fused kernel's if the windowed one won); best_ms: the best
  * time of probe_steps steps over all candidates (each may be NULL). With
  * d_scratch (device, >= 16 ny pitch doubles) the state is saved and
  * restored; with NULL the state advances. */
 lbm_status lbm_tune(lbm_handle* h, int64_t probe_steps, double* d_scratch, size_t scratch_bytes, int32_t* rows_out,
                     int32_t* waves_out, double* best_ms);
-/* Current tile shape (either pointer may be NULL). */
+/* Current tile shape of variant 0, or of variant 4 while the handle uses it
+ * (either pointer may be NULL). */
 lbm_status lbm_get_tile(const lbm_handle* h, int32_t* rows, int32_t* waves);
 
 /* Diagnostic, not part of the method: copies the 16 pitched planes of an

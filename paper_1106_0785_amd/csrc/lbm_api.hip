@@ -200,12 +200,26 @@ hipError_t launch_step2(const Field& F, const Hot* c, const Cold* cold, int vers
 }
 
 TileShape default_tile2(int nx, int ny) {
+  // two waves per workgroup (two workgroups per CU) and 16-row tiles were
+  // fastest at 4096 x 1024; shorter tiles while that leaves < 1024 tiles
   const long long strips = (nx + OSTRIP - 1) / OSTRIP;
-  int rows = 64;
-  while (rows > 8 && strips * ((ny + rows - 1) / rows) < 1024) rows /= 2;
+  int rows = 16;
+  while (rows > 2 && strips * ((ny + rows - 1) / rows) < 1024) rows /= 2;
   const long long bytes = (long long)nx * ny * 256;
   const int nt = (bytes > (32ll << 20) && bytes <= (512ll << 20)) ? 0 : 1;
-  return TileShape{rows, 4, nt};
+  return TileShape{rows, 2, nt};
+}
+
+// Default kernel of a problem: the whole grid in one workgroup when it fits,
+// windows for narrow grids, two steps per launch where both distribution
+// buffers exceed the 256 MB last-level cache (the step is then bound by HBM,
+// and the two-step kernel halves its traffic), else the one-step kernel.
+int default_variant(const lbm_params* p) {
+  if (small_problem(p)) return 2;
+  if (narrow_problem(p)) return 3;
+  const long long bytes = (long long)p->nx * p->ny * 256;
+  if (two_step_problem(p) && bytes > (512ll << 20)) return 4;
+  return 0;
 }
 
 // True when the whole grid fits the one-workgroup multi-step kernel.
@@ -382,7 +396,7 @@ lbm_status lbm_create(const lbm_params* p, void* d_workspace, size_t ws_bytes, v
   h->flag = (int*)(base + 2 * 16 * h->plane * sizeof(double));
   h->dev = (Consts*)(base + 2 * 16 * h->plane * sizeof(double) + 256);
   h->cur = 0;
-  h->variant = small_problem(p) ? 2 : narrow_problem(p) ? 3 : 0;
+  h->variant = default_variant(p);
   h->win = default_window(p);
   h->tile = default_tile(p->nx, p->ny);
   h->tile2 = default_tile2(p->nx, p->ny);
@@ -575,8 +589,13 @@ lbm_status lbm_tune(lbm_handle* h, int64_t probe_steps, double* d_scratch, size_
   if (d_scratch) e = hipMemcpyAsync(d_scratch, h->f[h->cur], state, hipMemcpyDeviceToDevice, h->stream);
   if (e != hipSuccess) return hip_fail(e, "saving the state");
   const int saved_cur = h->cur, saved_variant = h->variant;
-  // the windowed kernel competes with the fused one unless another variant was chosen
-  const bool windows = window_problem(&h->p) && (saved_variant == 0 || saved_variant == 3);
+  // the windowed and two-step kernels compete with the fused one unless
+  // another variant was chosen
+  const bool windows = window_problem(&h->p) && (saved_variant == 0 || saved_variant == 3 || saved_variant == 4);
+  const bool two_step = two_step_problem(&h->p) && (saved_variant == 0 || saved_variant == 3 || saved_variant == 4);
+  // the two-step kernel is timed over an even number of steps (an odd count
+  // would end with a one-step launch)
+  const int64_t probe2 = (probe_steps + 1) / 2 * 2;
   hipEvent_t t0 = nullptr, t1 = nullptr;
   e = hipEventCreate(&t0);
   if (e == hipSuccess) e = hipEventCreate(&t1);
@@ -587,13 +606,15 @@ lbm_status lbm_tune(lbm_handle* h, int64_t probe_steps, double* d_scratch, size_
   lbm_status st = LBM_OK;
   // probe_steps steps of the current configuration after a 2-step warm-up
   auto time_it = [&](float& ms) -> bool {
+    const int64_t n = h->variant == 4 ? probe2 : probe_steps;
     st = lbm_step(h, 2);
     if (st != LBM_OK) return false;
     e = hipEventRecord(t0, h->stream);
-    if (e == hipSuccess) st = lbm_step(h, probe_steps);
+    if (e == hipSuccess) st = lbm_step(h, n);
     if (e == hipSuccess) e = hipEventRecord(t1, h->stream);
     if (e == hipSuccess) e = hipEventSynchronize(t1);
     if (e == hipSuccess && st == LBM_OK) e = hipEventElapsedTime(&ms, t0, t1);
+    ms *= (float)probe_steps / (float)n;  // per probe_steps steps
     return e == hipSuccess && st == LBM_OK;
   };
   const int cand[] = {4, 8, 12, 16, 20, 24, 28, 32, 40, 48, 56, 64, 96, 128, 192, 256};
@@ -625,6 +646,41 @@ lbm_status lbm_tune(lbm_handle* h, int64_t probe_steps, double* d_scratch, size_
     if (!good) break;
   }
   h->tile = best;
+  TileShape best2 = h->tile2;
+  float best2_t = 1e30f;
+  if (good && two_step) {
+    // two steps per launch: 2 or 4 waves, tile heights down from the
+    // fastest of the fused kernel's list, plus heights that give just under
+    // one, two or three tiles per workgroup slot (two per CU)
+    h->variant = 4;
+    int rc[32];
+    int nrc = 0;
+    for (int r : cand) rc[nrc++] = r;
+    const long long strips = (h->p.nx + OSTRIP - 1) / OSTRIP;
+    for (int k = 1; k <= 3; ++k) {
+      const long long segs = std::max(1ll, (long long)k * 512 / strips);
+      rc[nrc++] = (int)std::min<long long>(1024, (h->p.ny + segs - 1) / segs);
+    }
+    for (int nt : {1, 0}) {
+      for (int wv : {2, 4}) {
+        int seen[32];
+        int nseen = 0;
+        for (int j = 0; j < nrc && good; ++j) {
+          const March2Geom g = march2_geom(h->p.nx, h->p.ny, TileShape{rc[j], wv, nt});
+          if (std::find(seen, seen + nseen, g.rows) != seen + nseen) continue;
+          seen[nseen++] = g.rows;
+          h->tile2 = TileShape{g.rows, wv, nt};
+          float ms = 0;
+          if (!(good = time_it(ms))) break;
+          if (ms < best2_t) {
+            best2_t = ms;
+            best2 = h->tile2;
+          }
+        }
+      }
+    }
+    h->tile2 = best2;
+  }
   if (good && windows) {
     // window shapes: narrow grids keep every row; others take 2-D windows
     int shapes[24][3];
@@ -654,10 +710,14 @@ lbm_status lbm_tune(lbm_handle* h, int64_t probe_steps, double* d_scratch, size_
   }
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
-  if (windows)
-    h->variant = best_win_t < best_t ? 3 : 0;
-  else
+  if (windows || two_step) {
+    h->variant = 0;
+    float bt = best_t;
+    if (best_win_t < bt) h->variant = 3, bt = best_win_t;
+    if (best2_t < bt) h->variant = 4, bt = best2_t;
+  } else {
     h->variant = saved_variant;
+  }
   if (e != hipSuccess) return hip_fail(e, "tuning run");
   if (st != LBM_OK) return st;
   if (d_scratch) {
@@ -666,9 +726,10 @@ lbm_status lbm_tune(lbm_handle* h, int64_t probe_steps, double* d_scratch, size_
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_fail(e, "restoring the state");
   }
-  if (rows_out) *rows_out = best.rows;
-  if (waves_out) *waves_out = best.waves;
-  if (best_ms) *best_ms = std::min(best_t, best_win_t);
+  const TileShape& kept = h->variant == 4 ? h->tile2 : best;
+  if (rows_out) *rows_out = kept.rows;
+  if (waves_out) *waves_out = kept.waves;
+  if (best_ms) *best_ms = std::min(best_t, std::min(best_win_t, best2_t));
   return LBM_OK;
 }
 

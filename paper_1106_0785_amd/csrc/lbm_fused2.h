@@ -164,7 +164,7 @@ __device__ __forceinline__ void fused2_tile(Field F, const Hot* __restrict__ hot
   };
   auto enter_row = [&](int yr, double* f, double ev) {
     fix_ghost(cold, sx, ysrc(yr), f);
-    to_ring0((yr - base0) % R, f, ev);
+    to_ring0((unsigned)(yr - base0) % R, f, ev);
   };
 
   // Prologue: ring 0 rows y0-2 .. y0+W-1 (wave w fills slots w and w + W < R).
@@ -183,8 +183,10 @@ __device__ __forceinline__ void fused2_tile(Field F, const Hot* __restrict__ hot
   bool ok = true;
   // Level n+1 at row `rs` from ring 0, for this lane's column.
   auto level1 = [&](int rs, double* out, double& ux, double& uy) {
-    const int s0 = (rs - base0) % R, sp = (rs + 1 - base0) % R, sm = (rs - 1 - base0) % R;
-    ConvLds<0, C0>::run(c, ring0[s0], ring0[sp], ring0[sm], lane + 1, lane + 2, lane, out);
+    const int s0 = (unsigned)(rs - base0) % R, sp = (unsigned)(rs + 1 - base0) % R,
+              sm = (unsigned)(rs - 1 - base0) % R;
+    // the collision's long dependency chain first; the convection's LDS
+    // reads and arithmetic can then fill its latencies
     double f[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) f[i] = ring0[s0][i][lane + 1];
@@ -197,7 +199,11 @@ __device__ __forceinline__ void fused2_tile(Field F, const Hot* __restrict__ hot
     nv.uy_yp = ring0[sp][17][lane + 1];
     nv.ux_ym = ring0[sm][16][lane + 1];
     nv.uy_ym = ring0[sm][17][lane + 1];
-    const bool good = collide_add<VER>(c, f, nv, out);
+    double df[16];
+    const bool good = collide_delta<VER>(c, f, nv, df);
+    ConvLds<0, C0>::run(c, ring0[s0], ring0[sp], ring0[sm], lane + 1, lane + 2, lane, out);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) out[i] = f[i] + (out[i] + df[i]);
     ok &= good || X < 0 || X >= nx || rs < 0 || rs >= ny;
     velocity_of(out, ux, uy);
   };
@@ -222,7 +228,7 @@ __device__ __forceinline__ void fused2_tile(Field F, const Hot* __restrict__ hot
     const int a = y0 - 1 + i * W + w;
     if (a <= y1) {
       double v[16] = {}, ux = 0.0, uy = 0.0;
-      const int slot = (a - base1) % R;
+      const int slot = (unsigned)(a - base1) % R;
       if (a >= 0 && a < ny) {
         level1(a, v, ux, uy);
         put_row(slot, v, ux, uy, -1, 0);
@@ -239,7 +245,7 @@ __device__ __forceinline__ void fused2_tile(Field F, const Hot* __restrict__ hot
             level1(rb, v, ux, uy);  // boundary row's inputs are in ring 0: compute it again
           } else {
             // computed in the previous iteration: read it back
-            const int sb = (rb - base1) % R;
+            const int sb = (unsigned)(rb - base1) % R;
 #pragma unroll
             for (int k = 0; k < 16; ++k) v[k] = ring1[sb][k][lane];
             ux = ring1[sb][16][lane];
@@ -261,10 +267,9 @@ __device__ __forceinline__ void fused2_tile(Field F, const Hot* __restrict__ hot
     // level n+2 at row b = a - 1
     const int b = a - 1;
     if (b >= y0 && b < y1) {
-      const int t0 = (b - base1) % R, tp = (b + 1 - base1) % R, tm = (b - 1 - base1) % R;
+      const int t0 = (unsigned)(b - base1) % R, tp = (unsigned)(b + 1 - base1) % R,
+                tm = (unsigned)(b - 1 - base1) % R;
       const int cl = lane > 0 ? lane - 1 : 0, cr = lane < 63 ? lane + 1 : 63;
-      double out[16];
-      ConvLds<0, C1>::run(c, ring1[t0], ring1[tp], ring1[tm], lane, cr, cl, out);
       double f[16];
 #pragma unroll
       for (int k = 0; k < 16; ++k) f[k] = ring1[t0][k][lane];
@@ -277,8 +282,12 @@ __device__ __forceinline__ void fused2_tile(Field F, const Hot* __restrict__ hot
       nv.uy_yp = ring1[tp][17][lane];
       nv.ux_ym = ring1[tm][16][lane];
       nv.uy_ym = ring1[tm][17][lane];
+      double df[16], out[16];
+      const bool good = collide_delta<VER>(c, f, nv, df);
+      ConvLds<0, C1>::run(c, ring1[t0], ring1[tp], ring1[tm], lane, cr, cl, out);
+#pragma unroll
+      for (int k = 0; k < 16; ++k) out[k] = f[k] + (out[k] + df[k]);
       const bool store = lane >= 1 && lane <= OSTRIP && X < nx;
-      const bool good = collide_add<VER>(c, f, nv, out);
       ok &= good || !store;
       if (store) {
         if constexpr (NT)

@@ -42,6 +42,7 @@ March2Geom march2_geom(int nx, int ny, TileShape t);
 hipError_t launch_step2(const Field& F, const Hot* c, const Cold* cold, int version, TileShape t, int* flag,
                         hipStream_t s);
 TileShape default_tile2(int nx, int ny);
+int default_variant(const lbm_params* p);
 // Small-grid and windowed kernels (lbm_multistep.h) and their selection
 // rules, as lbm_create applies them.
 bool small_problem(const lbm_params* p);

@@ -106,10 +106,10 @@ lbm_status lbm_run_noalloc(const lbm_params* p, const double* d_f_in, double* d_
     if (e != hipSuccess) return hip_fail(e, "copying the initial distributions in");
   }
   // the kernel lbm_create picks for this problem, with its default shape
-  const int variant = small_problem(p) ? 2 : narrow_problem(p) ? 3 : 0;
+  const int variant = default_variant(p);
   const bool walls = has_walls(p);
   const WinGeom win = default_window(p);
-  const TileShape tile = default_tile(p->nx, p->ny);
+  const TileShape tile = default_tile(p->nx, p->ny), tile2 = default_tile2(p->nx, p->ny);
   int cur = 0;
   int64_t n = 0;
   while (n < nsteps) {
@@ -127,6 +127,9 @@ lbm_status lbm_run_noalloc(const lbm_params* p, const double* d_f_in, double* d_
     } else if (variant == 3) {
       k = std::min<int64_t>(win.h, nsteps - n);
       e = launch_window(F, &consts->hot, &consts->cold, p->eq_version, walls, win, (int)k, flag, s);
+    } else if (variant == 4 && nsteps - n >= 2) {
+      k = 2;
+      e = launch_step2(F, &consts->hot, &consts->cold, p->eq_version, tile2, flag, s);
     } else {
       e = launch_step(F, &consts->hot, &consts->cold, p->eq_version, walls, p->scheme, 0, tile, flag, s);
     }

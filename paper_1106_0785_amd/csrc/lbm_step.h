@@ -127,11 +127,10 @@ struct ConvAll<16> {
                          double*) {}
 };
 
-// Collision of one node in velocity space, -dt M^-1 Q (Sec. II), added to
-// the increments `acc`, then the new distributions f + acc are written to
-// `acc`. Returns false when rho <= 0, T <= 0 or a NaN appears.
+// Collision of one node in velocity space, -dt M^-1 Q (Sec. II), into df.
+// Returns false when rho <= 0, T <= 0 or a NaN appears.
 template <int VER>
-LBM_HD bool collide_add(const Hot& c, const double* f, const NbrVel& nv, double* acc) {
+LBM_HD bool collide_delta(const Hot& c, const double* f, const NbrVel& nv, double* df) {
   double m[16];
   moments_from_f(f, m);
   const double rho = m[0], jx = m[1], jy = m[2], e = m[3];
@@ -152,11 +151,19 @@ LBM_HD bool collide_add(const Hot& c, const double* f, const NbrVel& nv, double*
     col[6] += c.cmod[0] * rT * ux * A + c.cmod[1] * rT * uy * B;
     col[7] += c.cmod[2] * rT * ux * B + c.cmod[3] * rT * uy * A;
   }
-  double df[16];
   f_from_nonconserved(col, df);
+  return (rho > 0.0) && (T > 0.0);
+}
+
+// The collision added to the convection increments `acc`; the new
+// distributions f + (acc + df) are written to `acc`.
+template <int VER>
+LBM_HD bool collide_add(const Hot& c, const double* f, const NbrVel& nv, double* acc) {
+  double df[16];
+  const bool ok = collide_delta<VER>(c, f, nv, df);
 #pragma unroll
   for (int i = 0; i < 16; ++i) acc[i] = f[i] + (acc[i] + df[i]);
-  return (rho > 0.0) && (T > 0.0);
+  return ok;
 }
 
 // New distributions at one interior node.

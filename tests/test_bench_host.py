@@ -14,12 +14,14 @@ def test_more_than_one_gpu_is_refused_with_a_message():
     assert "one GPU" in r.stderr and r.stdout == ""
 
 
-def test_traffic_record_names_the_fused_kernel():
+def test_traffic_record_names_the_two_step_kernel():
     sys.path.insert(0, ROOT)
     import bench
 
-    rec = bench.traffic_from_profiles("k_step_fused", "rm_4096x1024")
-    # either the record matches the current kernel sources (bytes per launch,
-    # within a few percent of the algorithmic 256 B per node) or it is null
-    assert rec is None or 0.95 < rec / (256 * 4096 * 1024) < 1.2
+    rec = bench.traffic_from_profiles("k_step_fused2", "rm_4096x1024")
+    # either the record matches the current kernel sources (bytes per launch
+    # of two steps: about the 256 B per node one step moves, plus the strips'
+    # overlap) or it is null
+    assert rec is None or 0.95 < rec / (256 * 4096 * 1024) < 1.25
     assert bench.traffic_from_profiles("k_step_window", "rm_4096x1024") is None
+    assert bench.traffic_from_profiles("k_step_fused", "rm_4096x1024") is None
