@@ -83,12 +83,19 @@ def build(force=False, variants=("plain", "fma", "reversed")):
 
 
 _libs = {}
+# A different build of the same source to load in place of the plain one
+# (a path; used to run the oracle's tests against an instrumented build).
+_OVERRIDE = os.environ.get("LBM_ORACLE_LIB")
 
 
 def _load(variant="plain"):
     if variant not in _libs:
-        build(variants=(variant,), force=(variant == "native"))
-        lib = ctypes.CDLL(_VARIANTS[variant])
+        if variant == "plain" and _OVERRIDE:
+            path = _OVERRIDE
+        else:
+            build(variants=(variant,), force=(variant == "native"))
+            path = _VARIANTS[variant]
+        lib = ctypes.CDLL(path)
         P = ctypes.POINTER(ctypes.c_double)
         pp = ctypes.POINTER(OracleParams)
         lib.oracle_matrices.argtypes = [P, P, P]
