@@ -373,6 +373,45 @@ def fig2_stability_sets(versions=(1,), modified=1):
     return params, states
 
 
+# The high-Mach shock tube of Sec. IV.B(a), Fig. 6: uniform states (rho, u_x,
+# u_y, T) on either side (Mach 10.1 and 6.3 with Ma = u / sqrt(2T)),
+# dx = dy = 0.003, dt = 1e-5, s5 = s6 = 1.5e4, every other rate 1e5.
+FIG6_STATES = {"left": (5.0, 45.0, 0.0, 10.0), "right": (6.0, -20.0, 0.0, 5.0)}
+
+
+def fig6_stability_sets(versions=(1, 2), modified=(0, 1), dt=1e-5, at_rest=False):
+    """(params list, base-state list, labels) for the two states of the
+    Fig. 6 shock tube under every equilibrium version and modification mode
+    given; at_rest: the same states with zero velocity."""
+    s = [1e5] * 16
+    s[4] = s[5] = 1.5e4
+    params, states, labels = [], [], []
+    for side, st in FIG6_STATES.items():
+        if at_rest:
+            st = (st[0], 0.0, 0.0, st[3])
+        for ver in versions:
+            for mod in modified:
+                params.append(params_of_stability(s, ver, mod, dx=0.003, dy=0.003, dt=dt))
+                states.append(st)
+                labels.append("%s v%d mod%d" % (side, ver, mod))
+    return params, states, labels
+
+
+def riemann_stability_sets(kind="lax", Prs=(0.5, 1.0, 2.0)):
+    """(params list, base-state list, labels): the two uniform states of a
+    shock-tube configuration (riemann() above) at each Prandtl number."""
+    L, R = RIEMANN_STATES[kind]
+    params, states, labels = [], [], []
+    for Pr in Prs:
+        p, _, _ = riemann(kind, Pr=Pr, nx=2000, ny=1)
+        q = params_of_stability(p["s"], 1, p["modified"], dx=p["dx"], dy=p["dy"], dt=p["dt"])
+        for side, st in (("left", L), ("right", R)):
+            params.append(q)
+            states.append((st[0], st[1], 0.0, st[2] / st[0]))
+            labels.append("%s Pr %g %s" % (kind, Pr, side))
+    return params, states, labels
+
+
 def params_of_stability(s, version=1, modified=1, dx=1e-3, dy=1e-3, dt=1e-5):
     return params(1, 1, dx, dy, dt, s, ["periodic"] * 4, eq_version=version, modified=modified)
 

@@ -156,3 +156,28 @@ def test_full_size_map_sampled():
     for k in range(len(p)):
         want = so.omega_max(p[k], s[k], th[idx])
         assert np.all(np.abs(r[k, idx] - want) <= TOL_R * want), k
+
+
+def test_radius_matches_oracle_on_shock_tube_states():
+    """The uniform states of the high-Mach shock tube of Sec. IV.B(a)
+    (Fig. 6; versions 1 and 2, modified or not) and of the configured Lax
+    tube at Pr 0.5 / 1 / 2: the library's |omega|_max equals the oracle's
+    along theta_y = 0 and theta_y = 0.5, and both show the Fig. 6 states and
+    the Lax tube's left state at Pr 0.5 unstable."""
+    p6, s6, l6 = inputs.fig6_stability_sets()
+    pl, sl, ll = inputs.riemann_stability_sets("lax")
+    p, s, labels = p6 + pl, s6 + sl, l6 + ll
+    tx = np.linspace(0.0, np.pi, 65)
+    th = np.concatenate([np.stack([tx, 0 * tx], 1), np.stack([tx, 0.5 + 0 * tx], 1)])
+    r, worst = _radius_check(p, s, th)
+    log("|omega|_max vs oracle on shock-tube states: worst rel %.2e; maxima %s" %
+        (worst, ", ".join("%s %.6f" % (lab, v) for lab, v in zip(labels, r.max(axis=1)))))
+    for lab, v in zip(labels, r.max(axis=1)):
+        if lab.startswith("left v"):
+            assert v > 1.015, lab
+        elif lab.startswith("right v"):
+            assert v > 1.001, lab
+        elif lab == "lax Pr 0.5 left":
+            assert v > 1.002, lab
+        else:
+            assert v <= 1.0 + TOL_R, (lab, v)

@@ -127,3 +127,76 @@ def test_chain_rule_matches_differentiating_the_node_path(version):
         qq, mac = oracle.node_equilibrium_complex(version, f)
         assert np.max(np.abs(qq.imag / H - jeq[:, j])) <= 1e-12 * max(1.0, np.max(np.abs(jeq)))
         assert abs(mac[1].imag / H - dux[j]) < 1e-13 and abs(mac[2].imag / H - duy[j]) < 1e-13
+
+
+def _line(n=129):
+    th = np.linspace(0.0, np.pi, n)
+    return np.stack([th, np.zeros_like(th)], axis=1)
+
+
+def test_fig6_states_are_linearly_unstable():
+    """The Mach-10.1 / 6.3 shock tube of Sec. IV.B(a) (Fig. 6) with the
+    paper's dx, dt and rates: each of its two uniform states is itself
+    unstable under this scheme (|omega|_max > 1 at mid wavenumbers), for
+    equilibrium versions 1 and 2, modified or not; at rest the same states
+    are stable. Growth per unit time ln|omega|/dt barely changes with dt, so
+    no smaller time step removes it: over the paper's t = 0.018 a
+    perturbation of the inflow state grows by ~1e14."""
+    th = _line()
+    p, s, labels = inputs.fig6_stability_sets()
+    for q, st, lab in zip(p, s, labels):
+        w = so.omega_max(q, st, th).max()
+        assert w > (1.015 if lab.startswith("left") else 1.001), (lab, w)
+    p, s, labels = inputs.fig6_stability_sets(at_rest=True)
+    for q, st, lab in zip(p, s, labels):
+        # 1 at theta = 0 (the conserved modes) up to the eigenvalue solver's
+        # rounding at these temperatures (~1e-12)
+        assert so.omega_max(q, st, th).max() <= 1.0 + 1e-10, lab
+    rates = []
+    for dt in (1e-5, 1e-6):
+        q, st, _ = inputs.fig6_stability_sets(versions=(1,), modified=(1,), dt=dt)
+        rates.append(np.log(so.omega_max(q[0], st[0], th).max()) / dt)
+    assert rates[0] > 1000.0 and abs(rates[1] / rates[0] - 1.0) < 0.1, rates
+    assert np.exp(rates[0] * 0.018) > 1e12
+
+
+def test_fig6_left_state_grows_in_the_oracle_step_as_predicted():
+    """The oracle's own step, on a periodic line in the Fig. 6 inflow state
+    with a density perturbation of 1e-7 at wavenumber 15 of 64 (theta =
+    1.47, near the most unstable one): once its dominant mode has taken over,
+    the perturbation grows by |omega(theta)| per step, as the amplification
+    matrix predicts."""
+    q, st, _ = inputs.fig6_stability_sets(versions=(1,), modified=(1,))
+    p = dict(q[0], nx=64, ny=1)
+    k = 15
+    theta = 2.0 * np.pi * k / 64
+    w = so.omega_max(q[0], st[0], np.array([[theta, 0.0]]))[0]
+    x = np.arange(64)
+    base = {n: np.full((1, 64), v) for n, v in zip(("rho", "ux", "uy", "T"), st[0])}
+    pert = dict(base, rho=base["rho"] * (1.0 + 1e-7 * np.cos(theta * x))[None, :])
+    f0 = oracle.init(p, **base)
+    fp = oracle.init(p, **pert)
+    a = oracle.run(p, fp, 150) - oracle.run(p, f0, 150)
+    b = oracle.run(p, fp, 350) - oracle.run(p, f0, 350)
+    growth = (np.linalg.norm(b) / np.linalg.norm(a)) ** (1.0 / 200)
+    assert w > 1.015
+    assert abs(growth / w - 1.0) < 2e-3, (growth, w)
+
+
+def test_lax_tube_is_unstable_only_at_prandtl_one_half():
+    """The configured Lax tube (Sec. IV.B(a) in spirit, 2000 x 4, dx = 5e-4,
+    dt = 1e-5, s5 = s6 = 1e4, s7 = s8 = 1e4 Pr): its left state (T = 7.9) is
+    unstable at Pr = 0.5 and stable at Pr = 1 and 2, its right state stable
+    at all three, and the Sod states stable at all three; the full-length
+    Lax run at Pr = 0.5 loses positivity in the oracle and on the GPU."""
+    th = _line()
+    p, s, labels = inputs.riemann_stability_sets("lax")
+    for q, st, lab in zip(p, s, labels):
+        w = so.omega_max(q, st, th).max()
+        if lab == "lax Pr 0.5 left":
+            assert w > 1.002, (lab, w)
+        else:
+            assert w <= 1.0 + 1e-12, (lab, w)
+    p, s, labels = inputs.riemann_stability_sets("sod")
+    for q, st, lab in zip(p, s, labels):
+        assert so.omega_max(q, st, th).max() <= 1.0 + 1e-12, lab
