@@ -52,6 +52,14 @@ lbm_status lbm_adjoint_backward(lbm_adjoint* a, const double* d_rho0, const doub
                                 const double* d_g_uy, const double* d_g_T, double* d_grad_rho0,
                                 double* d_grad_ux0, double* d_grad_uy0, double* d_grad_T0, double* d_grad_s);
 
+/* Kernel of the adjoint step: 0 the LDS-staged form (64-column tiles
+ * marching up the grid, lambda^{n+1} and the records entering an LDS ring
+ * once, ghost rules applied on entry; the default on large grids); 1 one
+ * thread per node gathering its neighbours' lambda and records from global
+ * memory (the default on small grids, where every tile would be a few rows
+ * tall). Both give the same results to rounding. */
+lbm_status lbm_adjoint_set_variant(lbm_adjoint* a, int32_t variant);
+
 /* Synchronises the stream and reads the device health flag of every step
  * the forward and reverse sweeps ran since the last check (the checkpointed
  * forward steps and the recomputed segments): LBM_OK, or LBM_ENONFINITE if

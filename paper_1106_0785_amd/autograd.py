@@ -28,6 +28,7 @@ def _lib():
             "lbm_adjoint_final_moments": ([P, P, P, P, P, P], ctypes.c_int),
             "lbm_adjoint_backward": ([P] + [P] * 13, ctypes.c_int),
             "lbm_adjoint_check": ([P], ctypes.c_int),
+            "lbm_adjoint_set_variant": ([P, ctypes.c_int32], ctypes.c_int),
             "lbm_adjoint_destroy": ([P], None),
         }
         for name, (args, res) in sigs.items():
@@ -65,6 +66,11 @@ class Adjoint:
         _check(_lib().lbm_adjoint_create(ctypes.byref(p), int(nsteps), int(ckpt_interval),
                                          ctypes.c_void_p(self.workspace.data_ptr()), nbytes, stream, ctypes.byref(h)))
         self.handle = h
+
+    def set_variant(self, v):
+        """0: the LDS-staged adjoint step (default on large grids); 1: one
+        thread per node (default on small grids)."""
+        _check(_lib().lbm_adjoint_set_variant(self.handle, int(v)))
 
     def _f(self, a):
         return a.detach().to(self.device, dtype=torch.float64).contiguous()

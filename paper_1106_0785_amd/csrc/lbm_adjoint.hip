@@ -8,7 +8,7 @@
 #include <new>
 
 #include "../../include/lbm_adjoint.h"
-#include "lbm_adjoint_kernels.h"
+#include "lbm_adjoint_fused.h"
 #include "lbm_internal.h"
 
 using namespace lbm;
@@ -74,6 +74,7 @@ struct lbm_adjoint {
   Consts host;
   AdjCoef adj;
   bool forward_done;
+  int variant;  // adjoint step: 0 LDS-staged tiles, 1 one thread per node, global gathers
   double* state(size_t off, int i) { return (double*)(base + off) + (size_t)i * 16 * L.plane; }
   double* ckpt(int k) { return state(L.ckpt, k); }
   double* seg(int j) { return state(L.seg, j); }
@@ -129,6 +130,11 @@ lbm_status lbm_adjoint_create(const lbm_params* p, int64_t nsteps, int32_t ckpt_
   a->stream = (hipStream_t)hip_stream;
   a->base = (char*)d_workspace;
   a->forward_done = false;
+  // the LDS-staged step where its tiles are tall (large grids: at 4096 x 1024
+  // it takes 507 us per step against 598 for the gather form); small grids
+  // give each tile one row per wavefront, and the gather form is faster
+  // there (12.9 against 15.8 us per step at 512 x 128)
+  a->variant = default_tile(p->nx, p->ny).rows >= 16 ? 0 : 1;
   make_coef(p, &a->host.hot, &a->host.cold);
   std::memset(&a->adj, 0, sizeof(a->adj));
   const double dt = p->dt, s5 = p->s[4], s6 = p->s[5], s7 = p->s[6], s8 = p->s[7];
@@ -170,14 +176,24 @@ lbm_status lbm_adjoint_forward(lbm_adjoint* a, const double* d_rho0, const doubl
     if (e != hipSuccess) return hip_fail(e, "k_init launch");
   }
   const int C = a->L.C, K = a->L.K;
+  // between checkpoints no intermediate state is kept, so where the problem
+  // takes the two-step kernel by default, steps go two per launch
+  const bool two = default_variant(&a->p) == 4;
+  const TileShape t2 = default_tile2(a->p.nx, a->p.ny);
   for (int k = 0; k < K; ++k) {
     const int64_t n0 = (int64_t)k * C, n1 = std::min<int64_t>(n0 + C, a->nsteps);
     const double* fin = a->ckpt(k);
-    for (int64_t n = n0; n < n1; ++n) {
-      double* fout = (n == n1 - 1) ? a->ckpt(k + 1) : a->seg((int)((n - n0) & 1));
-      hipError_t e = step_into(a, fin, fout);
+    int j = 0;
+    for (int64_t n = n0; n < n1;) {
+      const int64_t take = (two && n1 - n >= 2) ? 2 : 1;
+      double* fout = (n + take == n1) ? a->ckpt(k + 1) : a->seg(j);
+      hipError_t e = take == 2 ? launch_step2(a->field(fin, fout), a->dhot(), a->dcold(), a->p.eq_version, t2,
+                                              a->flag(), a->stream)
+                               : step_into(a, fin, fout);
       if (e != hipSuccess) return hip_fail(e, "forward step launch");
       fin = fout;
+      j ^= 1;
+      n += take;
     }
   }
   a->forward_done = true;
@@ -221,6 +237,10 @@ lbm_status lbm_adjoint_backward(lbm_adjoint* a, const double* d_rho0, const doub
   const bool wide = (long long)L.gx * L.gy > 2048;
   auto kstep = wide ? (ver == 2 ? k_adj_step<2, true> : ver == 3 ? k_adj_step<3, true> : k_adj_step<1, true>)
                     : (ver == 2 ? k_adj_step<2, false> : ver == 3 ? k_adj_step<3, false> : k_adj_step<1, false>);
+  // the LDS-staged step: 64-column tiles of 4 waves (at least 4 rows each, so
+  // there are no more tiles than the per-block partial slots)
+  auto kfused = ver == 2 ? k_adj_fused<2, 4, true> : ver == 3 ? k_adj_fused<3, 4, true> : k_adj_fused<1, 4, true>;
+  const MarchGeom ag = march_geom(a->p.nx, a->p.ny, TileShape{std::max(4, default_tile(a->p.nx, a->p.ny).rows), 4, 1});
   for (int k = L.K - 1; k >= 0; --k) {
     const int64_t n0 = (int64_t)k * L.C, n1 = std::min<int64_t>(n0 + L.C, a->nsteps);
     // recompute f^{n0+1} .. f^{n1-1} into the segment store (f^{n0} is the checkpoint)
@@ -248,8 +268,12 @@ lbm_status lbm_adjoint_backward(lbm_adjoint* a, const double* d_rho0, const doub
       }
       if (walls || n == n1 - 1)
         hipLaunchKernelGGL(krec, gblk, bblk, 0, a->stream, F, a->lam(cur), a->rec(rc), a->dhot());
-      hipLaunchKernelGGL(kstep, gblk, bblk, 0, a->stream, F, a->lam(cur), a->lam(cur ^ 1), a->rec(rc), a->dhot(),
-                         a->dcold(), a->dadj(), a->partials(), fprev, a->rec(rc ^ 1));
+      if (a->variant == 0)
+        hipLaunchKernelGGL(kfused, dim3(8 * ag.per_xcd), dim3(256), 0, a->stream, F, a->lam(cur), a->lam(cur ^ 1),
+                           a->rec(rc), a->dhot(), a->dcold(), a->dadj(), a->partials(), fprev, a->rec(rc ^ 1), ag);
+      else
+        hipLaunchKernelGGL(kstep, gblk, bblk, 0, a->stream, F, a->lam(cur), a->lam(cur ^ 1), a->rec(rc), a->dhot(),
+                           a->dcold(), a->dadj(), a->partials(), fprev, a->rec(rc ^ 1));
       e = hipGetLastError();
       if (e != hipSuccess) return hip_fail(e, "adjoint step launch");
       cur ^= 1;
@@ -278,6 +302,13 @@ lbm_status lbm_adjoint_backward(lbm_adjoint* a, const double* d_rho0, const doub
   }
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "adjoint finish launch");
+  return LBM_OK;
+}
+
+lbm_status lbm_adjoint_set_variant(lbm_adjoint* a, int32_t variant) {
+  if (!a) return fail(LBM_EINVAL, "adjoint handle is NULL");
+  if (variant != 0 && variant != 1) return fail(LBM_EINVAL, "adjoint variant must be 0 or 1");
+  a->variant = variant;
   return LBM_OK;
 }
 

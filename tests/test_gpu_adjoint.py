@@ -300,3 +300,47 @@ def test_forward_reports_lost_positivity():
     out = a.forward(*[torch.from_numpy(fl[k]).cuda() for k in ("rho", "ux", "uy", "T")])
     assert torch.isfinite(out["rho"]).all()
     a.close()
+
+
+@pytest.mark.parametrize("shape", [(23, 17), (70, 9), (1, 13), (130, 1), (64, 4), (129, 33)])
+@pytest.mark.parametrize("name", ["specular_x_periodic_y", "dirichlet_x", "neq_walls_y", "neq_walls_x_version3",
+                                  "zero_gradient_x_specular_y"])
+def test_lds_step_matches_gather_step(name, shape):
+    """The LDS-staged adjoint step against the one-thread-per-node form on
+    the same problem: every gradient entry to rounding (the per-tile
+    s-gradient sums run in another order). The other adjoint tests run
+    whichever form is the default for their grid."""
+    import torch
+
+    from paper_1106_0785_amd.autograd import Adjoint
+
+    bc, kw = CASES[name]
+    nx, ny = shape
+    if (nx == 1 and bc[0] != "periodic") or (ny == 1 and bc[2] != "periodic"):
+        pytest.skip("an axis of extent 1 must be periodic")
+    if ("neq_wall" in bc[:2] and nx < 3) or ("neq_wall" in bc[2:] and ny < 3):
+        pytest.skip("walls need 3 nodes")
+    p, fl = inputs.smooth_periodic(seed=31, nx=nx, ny=ny, amp=0.06, **kw)
+    p["bc"] = bc
+    p["wall"][0] = [1.03, 0.02, 0.0, 1.01]
+    p["wall"][1] = [1.0, 0.0, 0.05, 1.04]
+    p["wall"][2] = [1.0, -0.03, 0.0, 0.97]
+    p["wall"][3] = [1.0, 0.06, 0.0, 1.02]
+    rng = np.random.default_rng(7)
+    w_rho = torch.from_numpy(rng.standard_normal((ny, nx))).cuda()
+    w_T = torch.from_numpy(rng.standard_normal((ny, nx))).cuda()
+    f0 = [torch.from_numpy(np.ascontiguousarray(fl[k])).cuda() for k in ("rho", "ux", "uy", "T")]
+    res = []
+    for v in (0, 1):
+        a = Adjoint(p, 25, 6)
+        a.set_variant(v)
+        a.forward(*f0)
+        grads, gs = a.backward(w_rho, None, None, w_T)
+        res.append(([g.cpu().numpy() for g in grads], gs.cpu().numpy()))
+        a.close()
+    for k in range(4):
+        g0, g1 = res[0][0][k], res[1][0][k]
+        err = np.max(np.abs(g0 - g1)) / max(np.max(np.abs(g1)), 1e-300)
+        assert err <= 1e-12, (name, shape, k, err)
+    es = np.max(np.abs(res[0][1] - res[1][1])) / np.max(np.abs(res[1][1]))
+    assert es <= 1e-12, (name, shape, es)
