@@ -120,6 +120,25 @@ def bench_batch(steps, seed=0, n=512, plain=True, two_d=False):
     torch.cuda.synchronize()
     tb = start.elapsed_time(stop) / 1e3
     b.check()
+    # both launch forms of the line instances at the tuned schedule, each
+    # captured in a graph: one launch per block of h steps, and one
+    # persistent launch per equilibrium version with grid barriers between blocks
+    forms = {}
+    for name, pers in (("per_block", False), ("persistent", True)):
+        b.set_persistent(pers)
+        b.init([f for _, _, f in items])
+        b.step(steps)  # warm-up: graph capture
+        torch.cuda.synchronize()
+        b.init([f for _, _, f in items])
+        start.record()
+        b.step(steps)
+        stop.record()
+        torch.cuda.synchronize()
+        t = start.elapsed_time(stop) / 1e3
+        b.check()
+        forms[name] = {"seconds": t, "mlups": nodes * steps / t / 1e6}
+    forms["persistent"]["grid"] = b.persistent()["grid"]
+    b.set_persistent(sched["persistent"])
     # per-instance step budgets (seeded, uniform in [K/4, K]): instances stop at their own budget
     rng = np.random.default_rng(seed + 1)
     budgets = [int(v) for v in rng.integers(steps // 4, steps + 1, size=n)]
@@ -141,7 +160,9 @@ def bench_batch(steps, seed=0, n=512, plain=True, two_d=False):
            "batched_mlups": nodes * steps / tb / 1e6,
            "budgets_seconds": tbb, "budgets_node_steps": budget_node_steps,
            "budgets_mlups": budget_node_steps / tbb / 1e6,
-           "schedule": {k: sched[k] for k in ("region", "steps_per_launch", "chunks", "tile_rows", "tiles")}}
+           "schedule": {k: sched[k] for k in ("region", "steps_per_launch", "persistent", "chunks", "tile_rows",
+                                              "tiles")},
+           "launch_forms": forms}
     if not plain:
         return out
     sims = []

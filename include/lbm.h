@@ -36,7 +36,8 @@ typedef enum {
   LBM_ENOMEM = -2,      /* workspace too small */
   LBM_EHIP = -3,        /* a HIP runtime call failed */
   LBM_ESTATE = -4,      /* call not valid in the handle's current state */
-  LBM_ENONFINITE = -5   /* the device health flag saw rho <= 0, T <= 0 or NaN */
+  LBM_ENONFINITE = -5,  /* the device health flag saw rho <= 0, T <= 0 or NaN */
+  LBM_ETIMEOUT = -6     /* a bounded device-side wait gave up (lbm_batch.h); the state is invalid */
 } lbm_status;
 
 /* Boundary kind of one side of the domain. */

@@ -16,7 +16,10 @@
  * are ceil(K/h) launches over every chunk. The other instances ("tiled") are
  * cut into 64-column tiles of a common height and take one launch per step
  * and per (equilibrium version, variant: plain, NEQ walls, flux-limited)
- * group, every tile of every such instance in the same launch. One call of lbm_batch_step(b, K) is
+ * group, every tile of every such instance in the same launch. In the persistent form
+ * (lbm_batch_set_persistent) the line instances of one equilibrium version take ONE launch for
+ * all ceil(K/h) blocks: as many workgroups as are resident at once loop over the chunk list, and a
+ * device-wide barrier with a bounded wait separates the blocks. One call of lbm_batch_step(b, K) is
  * captured once in a hipGraph and replayed on later calls with the same K.
  * Results equal those of lbm_step with the fused kernel (variant 0) on each
  * instance alone: bitwise for tiled instances, within rounding (the same
@@ -72,20 +75,32 @@ lbm_status lbm_batch_get_f(lbm_batch* b, double* d_f);
 lbm_status lbm_batch_set_schedule(lbm_batch* b, int32_t region, int32_t steps_per_launch, int32_t use_graph);
 lbm_status lbm_batch_get_schedule(const lbm_batch* b, int32_t* region, int32_t* steps_per_launch, int32_t* nchunks);
 
+/* Launch form of the line instances: persistent = 1, one launch per equilibrium version for the
+ * whole of an lbm_batch_step call (grid = min(chunks, workgroups resident on the device), chunks
+ * taken round-robin, a grid barrier between blocks of h steps); 0, one launch per block (the
+ * form at creation). Results are bitwise the same. timeout_ms in [0, 60000] bounds each barrier
+ * wait (wall clock; 0 gives up at once, for tests of the error path): a wait that runs out
+ * raises a device error word, every workgroup leaves, and lbm_batch_check then returns
+ * LBM_ETIMEOUT (the state is invalid; re-initialise). Overlapping calls on one batch race.
+ * grid (get): workgroups of the largest persistent launch of the current schedule. */
+lbm_status lbm_batch_set_persistent(lbm_batch* b, int32_t persistent, double timeout_ms);
+lbm_status lbm_batch_get_persistent(lbm_batch* b, int32_t* persistent, int32_t* grid);
+
 /* Tile height of the tiled instances (rows per tile, a multiple of 4 in
  * [4, 4096]; an instance shorter than that is one tile high). Results do not
  * depend on it. ntiles = tiles per step over all tiled instances. */
 lbm_status lbm_batch_set_tile_rows(lbm_batch* b, int32_t rows);
 lbm_status lbm_batch_get_tile_rows(const lbm_batch* b, int32_t* rows, int32_t* ntiles);
 
-/* Autotuner: times every admissible (region, h) for probe_steps steps of the
- * line instances, then tile heights 8 ... 128 for probe_steps steps of the
+/* Autotuner: times every admissible (region, h), each in both launch forms, for probe_steps
+ * steps of the line instances, then tile heights 8 ... 128 for probe_steps steps of the
  * tiled instances, on the current state (synchronising the stream); restores
  * the state and keeps the fastest of each; *best_ms receives the sum of the
  * two best times. */
 lbm_status lbm_batch_tune(lbm_batch* b, int64_t probe_steps, double* best_ms);
 
-/* As lbm_check, for the batch. */
+/* As lbm_check, for the batch; LBM_ETIMEOUT (checked first, then cleared) if a persistent
+ * launch's barrier wait timed out since the last check. */
 lbm_status lbm_batch_check(lbm_batch* b);
 
 void lbm_batch_destroy(lbm_batch* b);

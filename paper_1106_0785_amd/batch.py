@@ -31,6 +31,9 @@ def _lib():
             "lbm_batch_get_f": ([P, P], ctypes.c_int),
             "lbm_batch_set_schedule": ([P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
             "lbm_batch_get_schedule": ([P] + [ctypes.POINTER(ctypes.c_int32)] * 3, ctypes.c_int),
+            "lbm_batch_set_persistent": ([P, ctypes.c_int32, ctypes.c_double], ctypes.c_int),
+            "lbm_batch_get_persistent": ([P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
+                                         ctypes.c_int),
             "lbm_batch_set_tile_rows": ([P, ctypes.c_int32], ctypes.c_int),
             "lbm_batch_get_tile_rows": ([P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
                                         ctypes.c_int),
@@ -151,6 +154,17 @@ class Batch:
         _check(_lib().lbm_batch_get_schedule(self.handle, ctypes.byref(r), ctypes.byref(h), ctypes.byref(c)))
         return {"region": r.value, "steps_per_launch": h.value, "chunks": c.value}
 
+    def set_persistent(self, persistent, timeout_ms=2000.0):
+        """Line instances: one persistent launch per equilibrium version for a
+        whole call (True) or one launch per block of h steps (False);
+        timeout_ms bounds each grid-barrier wait of the persistent launch."""
+        _check(_lib().lbm_batch_set_persistent(self.handle, int(persistent), float(timeout_ms)))
+
+    def persistent(self):
+        p, g = ctypes.c_int32(), ctypes.c_int32()
+        _check(_lib().lbm_batch_get_persistent(self.handle, ctypes.byref(p), ctypes.byref(g)))
+        return {"persistent": bool(p.value), "grid": g.value}
+
     def set_tile_rows(self, rows):
         _check(_lib().lbm_batch_set_tile_rows(self.handle, int(rows)))
 
@@ -171,15 +185,17 @@ class Batch:
                 cache = json.load(open(CACHE))
             except ValueError:
                 cache = {}
-        if use_cache and key in cache and "tile_rows" in cache[key]:
+        if use_cache and key in cache and "tile_rows" in cache[key] and "persistent" in cache[key]:
             c = cache[key]
             self.set_schedule(c["region"], c["steps_per_launch"])
+            self.set_persistent(c["persistent"])
             self.set_tile_rows(c["tile_rows"])
             return dict(c, cached=True)
         best = ctypes.c_double()
         _check(_lib().lbm_batch_tune(self.handle, int(probe_steps), ctypes.byref(best)))
         s = self.schedule()
         s.update(self.tile_rows())
+        s["persistent"] = self.persistent()["persistent"]
         s["probe_ms"] = best.value
         if use_cache:
             os.makedirs(os.path.dirname(CACHE), exist_ok=True)

@@ -17,6 +17,13 @@ namespace {
 
 constexpr int MIN_CHUNK = 32;
 
+// Device status words of a batch, each in a line of its own: health flag at
+// byte 0, barrier-timeout error at 64, the persistent launches' ticket
+// counter at 128, their barrier words (BAR_WORDS unsigned) from 256 (the
+// persistent kernel finds them from the flag's address).
+constexpr size_t STATUS_BYTES = 256 + 4 * BAR_WORDS;
+static_assert(STATUS_BYTES % 256 == 0, "the backup arena after the status words stays 256-byte aligned");
+
 struct Schedule {
   int region;  // 128 or 256 nodes per workgroup region
   int h;       // time steps per launch
@@ -32,6 +39,22 @@ void launch_line(const double* A, double* B, const LineInst* insts, const LineCh
   hipLaunchKernelGGL((k_batch_line<VER, REGION>), dim3(nchunks), dim3(REGION), 0, st, A, B, insts, chunks, budget, n0, h,
                      flag);
 }
+
+// Persistent line kernel of (version, region), as a function pointer.
+typedef void (*PersistentKernel)(double*, double*, const LineInst*, const LineChunk*, int, const int*, int, int, int*,
+                                 long long);
+
+PersistentKernel persistent_kernel(int ver, int region) {
+  if (region == 256)
+    return ver == 2 ? k_batch_line_persistent<2, 256> : ver == 3 ? k_batch_line_persistent<3, 256>
+                                                                 : k_batch_line_persistent<1, 256>;
+  return ver == 2 ? k_batch_line_persistent<2, 128> : ver == 3 ? k_batch_line_persistent<3, 128>
+                                                               : k_batch_line_persistent<1, 128>;
+}
+
+// Default bound on one grid-barrier wait of a persistent launch. A block of
+// h steps of a workgroup's share of the chunks takes well under a second.
+constexpr double DEFAULT_BARRIER_TIMEOUT_MS = 2000.0;
 
 }  // namespace
 
@@ -59,7 +82,11 @@ struct lbm_batch {
   int tbegin[4][3], tend[4][3];  // [version][variant: 0 plain, 1 NEQ walls, 2 flux-limited]
   int max_chunks;
   int* budget;
-  int* flag;
+  int* flag;       // health flag (flag[0]), first of the STATUS_BYTES status words
+  unsigned long long* ctr;  // chunk ticket counter of the persistent launches
+  int persistent;  // line instances: 1 one persistent launch per version, 0 one launch per h steps
+  long long timeout_ticks;  // bound on one barrier wait, wall-clock ticks
+  int resident[4][2];       // resident workgroups of the persistent kernel [version][region 128, 256]; 0 unknown
   int cur;   // current buffer of the line instances
   int cur2;  // current buffer of the tiled instances
   Schedule sched;
@@ -150,7 +177,7 @@ static lbm_status layout_of(const lbm_params* inst, int32_t n, Layout* L) {
   L->tiles_off = L->tinsts_off + align256((size_t)std::max(ntiled, 1) * sizeof(TileInst));
   L->budget_off = L->tiles_off + align256((size_t)std::max(ntiles, 1) * sizeof(int));
   L->flag_off = L->budget_off + align256((size_t)n * sizeof(int));
-  L->backup_off = L->flag_off + 256;
+  L->backup_off = L->flag_off + STATUS_BYTES;
   L->total = L->backup_off + L->arena_bytes;
   return LBM_OK;
 }
@@ -229,6 +256,25 @@ static lbm_status build_tiles(lbm_batch* b, int rows) {
   return LBM_OK;
 }
 
+// Workgroups of the persistent kernel of (version, region) resident on the
+// stream's device at once (all its compute units, the kernel alone).
+static hipError_t resident_workgroups(lbm_batch* b, int ver, int region, int* out) {
+  int& r = b->resident[ver][region == 256 ? 1 : 0];
+  if (r == 0) {
+    int dev = 0, ncu = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(persistent_kernel(ver, region)),
+                                                       region, 0);
+    if (e != hipSuccess) return e;
+    if (ncu < 1 || per_cu < 1) return hipErrorInvalidConfiguration;
+    r = ncu * per_cu;
+  }
+  *out = r;
+  return hipSuccess;
+}
+
 // Enqueues nsteps steps of every instance: the line instances as
 // ceil(nsteps / h) temporal-blocking launches starting from buffer
 // start_cur, the tiled instances as one launch per step and group starting
@@ -237,7 +283,24 @@ static hipError_t enqueue_steps(lbm_batch* b, int64_t nsteps, int start_cur, int
                                 int what = 3) {
   int cur = start_cur;
   const bool lines = (what & 1) && b->vend[3] > b->vbegin[1];
-  for (int64_t n0 = 0; lines && n0 < nsteps; n0 += b->sched.h) {
+  if (lines && b->persistent) {
+    // one launch per version runs every block; afterwards the lines' state
+    // is where ceil(nsteps / h) one-block launches would have left it
+    for (int ver = 1; ver <= 3; ++ver) {
+      const int nc = b->vend[ver] - b->vbegin[ver];
+      if (nc == 0) continue;
+      int cap = 0;
+      hipError_t e = resident_workgroups(b, ver, b->sched.region, &cap);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(k_persist_reset, dim3(1), dim3(1), 0, stream, b->ctr);
+      hipLaunchKernelGGL(persistent_kernel(ver, b->sched.region), dim3(std::min(nc, cap)), dim3(b->sched.region), 0,
+                         stream, b->arena[start_cur], b->arena[start_cur ^ 1], b->insts, b->chunks + b->vbegin[ver], nc,
+                         b->budget, (int)nsteps, b->sched.h, b->flag, b->timeout_ticks);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+  }
+  for (int64_t n0 = 0; lines && !b->persistent && n0 < nsteps; n0 += b->sched.h) {
     const int h = (int)std::min<int64_t>(b->sched.h, nsteps - n0);
     for (int ver = 1; ver <= 3; ++ver) {
       const int nc = b->vend[ver] - b->vbegin[ver];
@@ -324,6 +387,9 @@ lbm_status lbm_batch_create(const lbm_params* inst, int32_t n, void* d_workspace
   b->tile_inst = (int*)(base + L.tiles_off);
   b->budget = (int*)(base + L.budget_off);
   b->flag = (int*)(base + L.flag_off);
+  b->ctr = (unsigned long long*)(base + L.flag_off + 128);
+  b->persistent = 0;
+  std::memset(b->resident, 0, sizeof(b->resident));
   b->backup = (double*)(base + L.backup_off);
   b->max_chunks = L.max_chunks;
   b->arena_doubles = L.arena_doubles;
@@ -338,6 +404,15 @@ lbm_status lbm_batch_create(const lbm_params* inst, int32_t n, void* d_workspace
     b->graph_steps[k] = -1;
   }
   b->capture = nullptr;
+  {
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess ||
+        khz < 1) {
+      delete b;
+      return hip_fail(hipGetLastError(), "reading the wall-clock rate");
+    }
+    b->timeout_ticks = (long long)(DEFAULT_BARRIER_TIMEOUT_MS * khz);
+  }
   if (hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking) != hipSuccess) {
     delete b;
     return hip_fail(hipGetLastError(), "creating the capture stream");
@@ -379,7 +454,7 @@ lbm_status lbm_batch_create(const lbm_params* inst, int32_t n, void* d_workspace
   std::vector<int> budget(n, INT_MAX);
   hipError_t e = hipMemcpyAsync(b->insts, b->host_insts.data(), n * sizeof(LineInst), hipMemcpyHostToDevice, b->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(b->budget, budget.data(), n * sizeof(int), hipMemcpyHostToDevice, b->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(b->flag, 0, 256, b->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(b->flag, 0, STATUS_BYTES, b->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) {
     (void)hipStreamDestroy(b->capture);
@@ -553,6 +628,38 @@ lbm_status lbm_batch_get_schedule(const lbm_batch* b, int32_t* region, int32_t* 
   return LBM_OK;
 }
 
+lbm_status lbm_batch_set_persistent(lbm_batch* b, int32_t persistent, double timeout_ms) {
+  if (!b) return fail(LBM_EINVAL, "batch is NULL");
+  if (persistent != 0 && persistent != 1) return fail(LBM_EINVAL, "persistent must be 0 or 1");
+  if (!(timeout_ms >= 0.0) || timeout_ms > 60000.0) return fail(LBM_EINVAL, "timeout_ms must be in [0, 60000]");
+  int dev = 0, khz = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+  if (e != hipSuccess) return hip_fail(e, "reading the wall-clock rate");
+  b->persistent = persistent;
+  b->timeout_ticks = (long long)(timeout_ms * khz);
+  drop_graphs(b);
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_get_persistent(lbm_batch* b, int32_t* persistent, int32_t* grid) {
+  if (!b) return fail(LBM_EINVAL, "batch is NULL");
+  if (persistent) *persistent = b->persistent;
+  if (grid) {
+    int g = 0;
+    for (int ver = 1; ver <= 3; ++ver) {
+      const int nc = b->vend[ver] - b->vbegin[ver];
+      if (nc == 0) continue;
+      int cap = 0;
+      hipError_t e = resident_workgroups(b, ver, b->sched.region, &cap);
+      if (e != hipSuccess) return hip_fail(e, "occupancy query");
+      g = std::max(g, std::min(nc, cap));
+    }
+    *grid = g;
+  }
+  return LBM_OK;
+}
+
 lbm_status lbm_batch_tune(lbm_batch* b, int64_t probe_steps, double* best_ms) {
   if (!b) return fail(LBM_EINVAL, "batch is NULL");
   if (probe_steps < 1) return fail(LBM_EINVAL, "probe_steps must be >= 1");
@@ -571,39 +678,52 @@ lbm_status lbm_batch_tune(lbm_batch* b, int64_t probe_steps, double* best_ms) {
     return hip_fail(e, "hipEventCreate");
   }
   Schedule best{256, 16};
+  int best_pers = b->persistent;
   float best_t = 1e30f;
   const int regions[2] = {128, 256};
   const int hs[6] = {4, 8, 12, 16, 24, 32};
+  struct Trial {
+    Schedule s;
+    int pers;
+  };
+  std::vector<Trial> trials;
   for (int r : regions)
-    for (int h : hs) {
-      Schedule s{r, h};
-      if (!schedule_ok(s)) continue;
-      if (build_chunks(b, s) != LBM_OK) continue;
-      // warm-up + timed trial, both without graphs
-      e = enqueue_steps(b, std::min<int64_t>(probe_steps, 2 * h), b->cur, b->cur2, b->stream, 1);
-      if (e == hipSuccess) e = hipEventRecord(t0, b->stream);
-      if (e == hipSuccess) e = enqueue_steps(b, probe_steps, b->cur, b->cur2, b->stream, 1);
-      if (e == hipSuccess) e = hipEventRecord(t1, b->stream);
-      if (e == hipSuccess) e = hipEventSynchronize(t1);
-      if (e != hipSuccess) break;
-      float ms = 0;
-      e = hipEventElapsedTime(&ms, t0, t1);
-      if (e != hipSuccess) break;
-      if (ms < best_t) {
-        best_t = ms;
-        best = s;
-      }
-      // restore the state for the next trial
-      e = hipMemcpyAsync(b->arena[saved_cur], b->backup, bytes, hipMemcpyDeviceToDevice, b->stream);
-      if (e != hipSuccess) break;
+    for (int h : hs)
+      for (int pers = 0; pers < 2; ++pers)
+        if (schedule_ok(Schedule{r, h})) trials.push_back(Trial{Schedule{r, h}, pers});
+  for (const Trial& tr : trials) {
+    if (build_chunks(b, tr.s) != LBM_OK) continue;
+    b->persistent = tr.pers;
+    // warm-up + timed trial, both without graphs
+    e = enqueue_steps(b, std::min<int64_t>(probe_steps, 2 * tr.s.h), b->cur, b->cur2, b->stream, 1);
+    if (e == hipSuccess) e = hipEventRecord(t0, b->stream);
+    if (e == hipSuccess) e = enqueue_steps(b, probe_steps, b->cur, b->cur2, b->stream, 1);
+    if (e == hipSuccess) e = hipEventRecord(t1, b->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(t1);
+    if (e != hipSuccess) break;
+    float ms = 0;
+    e = hipEventElapsedTime(&ms, t0, t1);
+    if (e != hipSuccess) break;
+    if (ms < best_t) {
+      best_t = ms;
+      best = tr.s;
+      best_pers = tr.pers;
     }
+    // restore the state for the next trial
+    e = hipMemcpyAsync(b->arena[saved_cur], b->backup, bytes, hipMemcpyDeviceToDevice, b->stream);
+    if (e != hipSuccess) break;
+  }
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
   if (e == hipSuccess) e = hipMemcpyAsync(b->arena[saved_cur], b->backup, bytes, hipMemcpyDeviceToDevice, b->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(b->flag, 0, sizeof(int), b->stream);
+  int word[17] = {0};  // a timed-out barrier in a trial voids the persistent form
+  if (e == hipSuccess) e = hipMemcpyAsync(word, b->flag, sizeof(word), hipMemcpyDeviceToHost, b->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(b->flag, 0, STATUS_BYTES, b->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) return hip_fail(e, "tuning run");
+  if (word[16]) return fail(LBM_ETIMEOUT, "a grid barrier of a persistent trial timed out");
   b->cur = saved_cur;
+  b->persistent = best_pers;
   lbm_status st = build_chunks(b, best);
   if (st != LBM_OK) return st;
   if (b->host_tinsts.empty()) {
@@ -668,10 +788,17 @@ lbm_status lbm_batch_get_tile_rows(const lbm_batch* b, int32_t* rows, int32_t* n
 
 lbm_status lbm_batch_check(lbm_batch* b) {
   if (!b) return fail(LBM_EINVAL, "batch is NULL");
-  int flag = 0;
-  hipError_t e = hipMemcpyAsync(&flag, b->flag, sizeof(int), hipMemcpyDeviceToHost, b->stream);
+  int word[17] = {0};  // flag at 0, err at 16
+  hipError_t e = hipMemcpyAsync(word, b->flag, sizeof(word), hipMemcpyDeviceToHost, b->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) return hip_fail(e, "reading the health flag");
+  const int flag = word[0];
+  if (word[16]) {  // a barrier wait timed out: clear err, the barrier and the flag
+    e = hipMemsetAsync(b->flag, 0, STATUS_BYTES, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
+    return fail(LBM_ETIMEOUT, "a grid barrier of the persistent launch timed out; the state is invalid");
+  }
   if (flag) {
     e = hipMemsetAsync(b->flag, 0, sizeof(int), b->stream);
     if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");

@@ -45,15 +45,20 @@ __device__ __forceinline__ void line_ghost(const LineInst& I, const Hot& c, int 
   }
 }
 
-template <int VER, int REGION>
-__global__ __launch_bounds__(REGION, 2) void k_batch_line(const double* __restrict__ A, double* __restrict__ B,
-                                                          const LineInst* __restrict__ insts,
-                                                          const LineChunk* __restrict__ chunks,
-                                                          const int* __restrict__ budget, int n0, int h,
-                                                          int* flag) {
+// One chunk (index ci of the chunk list) for up to h steps from step n0 of
+// the call: A -> B. Every thread of the workgroup calls it (it holds
+// barriers); returns false if a node lost positivity. With TICKET, thread 0
+// also takes the workgroup's next ticket from *ctr once the chunk is loaded
+// (so that the atomic's latency hides behind the time steps) and leaves it
+// in *tk_out (LDS) at the end.
+template <int VER, int REGION, bool TICKET = false>
+__device__ __forceinline__ bool line_chunk(const double* __restrict__ A, double* __restrict__ B,
+                                           const LineInst* __restrict__ insts, const LineChunk* __restrict__ chunks,
+                                           int ci, const int* __restrict__ budget, int n0, int h,
+                                           unsigned long long* ctr = nullptr, unsigned long long* tk_out = nullptr) {
   __shared__ double buf[2][NV][REGION];
   __shared__ Hot hs;
-  const LineChunk ch = chunks[blockIdx.x];
+  const LineChunk ch = chunks[ci];
   const LineInst& I = insts[ch.inst];
   const int t = threadIdx.x;
   const int N = I.N;
@@ -62,10 +67,11 @@ __global__ __launch_bounds__(REGION, 2) void k_batch_line(const double* __restri
   int steps = budget[ch.inst] - n0;
   steps = steps < 0 ? 0 : (steps > h ? h : steps);
   if (steps == 0) {  // nothing to do this block: carry the chunk over to the output buffer
+    if (TICKET && t == 0) *tk_out = __hip_atomic_fetch_add(ctr, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (int r = t; r < ch.len; r += REGION)
 #pragma unroll
       for (int i = 0; i < 16; ++i) B[off + (long long)i * stride + ch.start + r] = A[off + (long long)i * stride + ch.start + r];
-    return;
+    return true;
   }
   stage_hot(&I.hot, &hs);
   const Hot& c = hs;
@@ -87,6 +93,8 @@ __global__ __launch_bounds__(REGION, 2) void k_batch_line(const double* __restri
     buf[0][17][t] = uy;
   }
   __syncthreads();
+  unsigned long long next = 0;
+  if (TICKET && t == 0) next = __hip_atomic_fetch_add(ctr, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const int g = lo + t;  // line node of this thread
   const bool wall_lo = c.bc[2 * I.axis] == BC_NEQ_WALL, wall_hi = c.bc[2 * I.axis + 1] == BC_NEQ_WALL;
   bool ok = true;
@@ -164,8 +172,151 @@ __global__ __launch_bounds__(REGION, 2) void k_batch_line(const double* __restri
 #pragma unroll
     for (int i = 0; i < 16; ++i) B[off + (long long)i * stride + g] = buf[P][i][t];
   }
-  if (!ok) flag[0] = 1;
+  if (TICKET && t == 0) *tk_out = next;
+  return ok;
 }
+
+template <int VER, int REGION>
+__global__ __launch_bounds__(REGION, 2) void k_batch_line(const double* __restrict__ A, double* __restrict__ B,
+                                                          const LineInst* __restrict__ insts,
+                                                          const LineChunk* __restrict__ chunks,
+                                                          const int* __restrict__ budget, int n0, int h,
+                                                          int* flag) {
+  if (!line_chunk<VER, REGION>(A, B, insts, chunks, blockIdx.x, budget, n0, h)) flag[0] = 1;
+}
+
+// Grid-wide barrier of a persistent launch (every workgroup resident at
+// once), arranged as a two-level tree so that no counter takes more than
+// ~32 arrivals (arrivals on one device-scope counter are serialised, and a
+// flat counter over 512-1024 workgroups costs tens of microseconds).
+// Workgroup b belongs to group b mod G, G = min(BAR_GROUPS, grid). Words,
+// each group's in lines of their own (unsigned, stride BAR_STRIDE):
+//   bar[0]                              groups arrived (top counter)
+//   bar[BAR_STRIDE (1 + g)]             arrivals of group g
+//   bar[BAR_STRIDE (1 + g) + STRIDE/2]  generation seen by group g
+// The last arrival of a group arrives at the top counter; the last group
+// to arrive there advances every group's generation, which the group's
+// members poll. Stores before the barrier are released and loads after it
+// acquired at device (agent) scope, which spans the L2 caches of all XCDs;
+// every counter is back at 0 after a barrier that completes. The wait is
+// bounded: a workgroup that has waited `timeout` ticks of the constant-rate
+// wall clock (timeout 0: any workgroup that would wait) raises err[0] and
+// gives up, and every workgroup that sees err[0] raised leaves too, so the
+// launch always ends; the host reports the error and the state is invalid.
+constexpr int BAR_GROUPS = 32;
+constexpr int BAR_STRIDE = 64;  // unsigned words: 256 bytes
+constexpr int BAR_WORDS = BAR_STRIDE * (1 + BAR_GROUPS);
+
+__device__ __forceinline__ bool grid_barrier(unsigned* bar, int* err, long long timeout) {
+  __shared__ int ok_s;
+  __syncthreads();  // the whole workgroup's stores are issued and complete
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    const unsigned G = min((unsigned)BAR_GROUPS, gridDim.x);
+    const unsigned g = blockIdx.x % G;
+    const unsigned members = (gridDim.x - g + G - 1) / G;
+    unsigned* cnt = bar + BAR_STRIDE * (1 + g);
+    unsigned* gen_p = cnt + BAR_STRIDE / 2;
+    // Only fences order memory; the counters themselves are relaxed (a
+    // fence plus a relaxed atomic synchronises like a release or acquire
+    // atomic, and each fence costs an L2 write-back or invalidate).
+    // (the generation is read before the release, which keeps the read
+    // ahead of this workgroup's arrival)
+    const unsigned gen = __hip_atomic_load(gen_p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    bool wait = true;
+    if (__hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == members - 1) {
+      __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");  // the group's arrivals, passed on
+      if (__hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == G - 1) {
+        __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");  // every group's arrivals, passed on
+        for (unsigned k = 0; k < G; ++k)
+          __hip_atomic_store(bar + BAR_STRIDE * (1 + k) + BAR_STRIDE / 2, gen + 1u, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+        wait = false;
+      }
+    }
+    if (wait) {
+      if (timeout <= 0) {  // no wait allowed: give up
+        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+      } else {
+        const long long t0 = wall_clock64();
+        for (unsigned n = 1; __hip_atomic_load(gen_p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen; ++n) {
+          if ((n & 7) == 0 &&
+              (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) || wall_clock64() - t0 >= timeout)) {
+            __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ok = 0;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
+    ok_s = ok;
+  }
+  __syncthreads();
+  return ok_s != 0;
+}
+
+// A value every lane holds alike (read from LDS), marked workgroup-uniform
+// so that what derives from it (the chunk and its instance) stays in scalar
+// registers and uniform branches.
+__device__ __forceinline__ unsigned long long uniform_u64(unsigned long long v) {
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// Persistent form of the line kernel: one launch advances every chunk of
+// one equilibrium version through all the ceil(nsteps / h) blocks of h
+// steps of a call. The grid holds at most as many workgroups as are
+// resident on the device at once, and a grid barrier separates the blocks
+// (a chunk's halo comes from its neighbours' output of the block before).
+// Chunks are handed out in ticket order from one counter (ctr, zero at
+// launch): ticket k is chunk k mod nchunks of block k / nchunks, so the
+// workgroups balance the load as the hardware dispatcher would. A
+// workgroup fetches its next ticket while it works on a chunk; a ticket of
+// the next block is kept until the barrier is passed (there are at most
+// grid <= nchunks such tickets, so they all fall in the next block).
+// src: the buffer holding the state at the start, dst the other one.
+// status: the batch's status words (health flag at word 0, error word at
+// 16, ticket counter at 32, barrier words from 64).
+template <int VER, int REGION>
+__global__ __launch_bounds__(REGION, 2) void k_batch_line_persistent(double* src, double* dst,
+                                                                     const LineInst* __restrict__ insts,
+                                                                     const LineChunk* __restrict__ chunks, int nchunks,
+                                                                     const int* __restrict__ budget, int nsteps, int h,
+                                                                     int* status, long long timeout) {
+  unsigned long long* ctr = reinterpret_cast<unsigned long long*>(status + 32);
+  bool ok = true;
+  __shared__ unsigned long long tk_s[2];
+  if (threadIdx.x == 0) tk_s[0] = __hip_atomic_fetch_add(ctr, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  unsigned long long tk = uniform_u64(tk_s[0]);
+  int par = 1;
+  for (int n0 = 0, blk = 0; n0 < nsteps; n0 += h, ++blk) {
+    const int hb = min(h, nsteps - n0);
+    const double* A = (blk & 1) ? dst : src;
+    double* B = (blk & 1) ? src : dst;
+    const unsigned long long first = (unsigned long long)blk * (unsigned long long)nchunks, end = first + nchunks;
+    while (tk < end) {
+      ok &= line_chunk<VER, REGION, true>(A, B, insts, chunks, (int)(tk - first), budget, n0, hb, ctr, &tk_s[par]);
+      __syncthreads();  // also: this chunk is done with the LDS buffers
+      tk = uniform_u64(tk_s[par]);
+      par ^= 1;
+    }
+    if (n0 + h < nsteps && !grid_barrier(reinterpret_cast<unsigned*>(status + 64), status + 16, timeout)) break;
+  }
+  if (!ok) status[0] = 1;
+}
+
+// Zeroes the ticket counter of a persistent launch (a kernel, so that it can
+// sit in a captured graph).
+__global__ void k_persist_reset(unsigned long long* ctr) { *ctr = 0ull; }
 
 }  // namespace lbm
 

@@ -15,7 +15,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
 BC = {"periodic": 0, "zero_gradient": 1, "specular": 2, "neq_wall": 3, "dirichlet_eq": 4}
-STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EHIP", -4: "LBM_ESTATE", -5: "LBM_ENONFINITE"}
+STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EHIP", -4: "LBM_ESTATE", -5: "LBM_ENONFINITE",
+          -6: "LBM_ETIMEOUT"}
 
 
 class LbmError(RuntimeError):
