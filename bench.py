@@ -124,7 +124,7 @@ def bench_batch(steps, seed=0, n=512, plain=True, two_d=False):
     # captured in a graph: one launch per block of h steps, and one
     # persistent launch per equilibrium version with grid barriers between blocks
     forms = {}
-    for name, pers in (("per_block", False), ("persistent", True)):
+    for name, pers in (("per_block", False), ("persistent", True)) if sched["chunks"] else ():
         b.set_persistent(pers)
         b.init([f for _, _, f in items])
         b.step(steps)  # warm-up: graph capture
@@ -137,8 +137,9 @@ def bench_batch(steps, seed=0, n=512, plain=True, two_d=False):
         t = start.elapsed_time(stop) / 1e3
         b.check()
         forms[name] = {"seconds": t, "mlups": nodes * steps / t / 1e6}
-    forms["persistent"]["grid"] = b.persistent()["grid"]
-    b.set_persistent(sched["persistent"])
+    if forms:
+        forms["persistent"]["grid"] = b.persistent()["grid"]
+        b.set_persistent(sched["persistent"])
     # per-instance step budgets (seeded, uniform in [K/4, K]): instances stop at their own budget
     rng = np.random.default_rng(seed + 1)
     budgets = [int(v) for v in rng.integers(steps // 4, steps + 1, size=n)]
@@ -161,8 +162,9 @@ def bench_batch(steps, seed=0, n=512, plain=True, two_d=False):
            "budgets_seconds": tbb, "budgets_node_steps": budget_node_steps,
            "budgets_mlups": budget_node_steps / tbb / 1e6,
            "schedule": {k: sched[k] for k in ("region", "steps_per_launch", "persistent", "chunks", "tile_rows",
-                                              "tiles")},
-           "launch_forms": forms}
+                                              "tiles", "two_step", "tile_rows2", "tiles2")}}
+    if forms:
+        out["launch_forms"] = forms
     if not plain:
         return out
     sims = []

@@ -16,14 +16,16 @@
  * are ceil(K/h) launches over every chunk. The other instances ("tiled") are
  * cut into 64-column tiles of a common height and take one launch per step
  * and per (equilibrium version, variant: plain, NEQ walls, flux-limited)
- * group, every tile of every such instance in the same launch. In the persistent form
+ * group, every tile of every such instance in the same launch; in two-step mode
+ * (lbm_batch_set_two_step) the plain ones (Lax-Wendroff, no NEQ walls) take two steps per launch
+ * through the two-step kernel of lbm_set_variant(4). In the persistent form
  * (lbm_batch_set_persistent) the line instances of one equilibrium version take ONE launch for
  * all ceil(K/h) blocks: as many workgroups as are resident at once loop over the chunk list, and a
  * device-wide barrier with a bounded wait separates the blocks. One call of lbm_batch_step(b, K) is
  * captured once in a hipGraph and replayed on later calls with the same K.
- * Results equal those of lbm_step with the fused kernel (variant 0) on each
- * instance alone: bitwise for tiled instances, within rounding (the same
- * arithmetic, multiply-adds contracted differently) for lines.
+ * Results equal those of lbm_step on each instance alone: with the fused kernel (variant 0)
+ * bitwise for tiled instances (in two-step mode the plain ones with variant 4, bitwise), within
+ * rounding (the same arithmetic, multiply-adds contracted differently) for lines.
  */
 #ifndef LBM_BATCH_H_
 #define LBM_BATCH_H_
@@ -92,11 +94,17 @@ lbm_status lbm_batch_get_persistent(lbm_batch* b, int32_t* persistent, int32_t* 
 lbm_status lbm_batch_set_tile_rows(lbm_batch* b, int32_t rows);
 lbm_status lbm_batch_get_tile_rows(const lbm_batch* b, int32_t* rows, int32_t* ntiles);
 
+/* Two-step mode of the plain tiled instances: on = 1, two steps per launch with `rows` output
+ * rows per two-step tile (even, in [2, 4096]; results do not depend on it); 0, one step per
+ * launch (the mode at creation). Can change between calls. ntiles = two-step tiles. */
+lbm_status lbm_batch_set_two_step(lbm_batch* b, int32_t on, int32_t rows);
+lbm_status lbm_batch_get_two_step(const lbm_batch* b, int32_t* on, int32_t* rows, int32_t* ntiles);
+
 /* Autotuner: times every admissible (region, h), each in both launch forms, for probe_steps
- * steps of the line instances, then tile heights 8 ... 128 for probe_steps steps of the
- * tiled instances, on the current state (synchronising the stream); restores
- * the state and keeps the fastest of each; *best_ms receives the sum of the
- * two best times. */
+ * steps of the line instances, then tile heights 8 ... 128 (one step per launch) and, with
+ * plain tiled instances, two-step tile heights 8 ... 128 for probe_steps steps of the tiled
+ * instances, on the current state (synchronising the stream); restores the state and keeps
+ * the fastest of each; *best_ms receives the sum of the two best times. */
 lbm_status lbm_batch_tune(lbm_batch* b, int64_t probe_steps, double* best_ms);
 
 /* As lbm_check, for the batch; LBM_ETIMEOUT (checked first, then cleared) if a persistent

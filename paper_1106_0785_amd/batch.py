@@ -35,6 +35,8 @@ def _lib():
             "lbm_batch_get_persistent": ([P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
                                          ctypes.c_int),
             "lbm_batch_set_tile_rows": ([P, ctypes.c_int32], ctypes.c_int),
+            "lbm_batch_set_two_step": ([P, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
+            "lbm_batch_get_two_step": ([P] + [ctypes.POINTER(ctypes.c_int32)] * 3, ctypes.c_int),
             "lbm_batch_get_tile_rows": ([P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
                                         ctypes.c_int),
             "lbm_batch_tune": ([P, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
@@ -173,6 +175,16 @@ class Batch:
         _check(_lib().lbm_batch_get_tile_rows(self.handle, ctypes.byref(r), ctypes.byref(t)))
         return {"tile_rows": r.value, "tiles": t.value}
 
+    def set_two_step(self, on, rows=32):
+        """Plain tiled instances: two steps per launch (on) with `rows`
+        output rows per two-step tile, or one step per launch."""
+        _check(_lib().lbm_batch_set_two_step(self.handle, int(on), int(rows)))
+
+    def two_step(self):
+        o, r, t = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(_lib().lbm_batch_get_two_step(self.handle, ctypes.byref(o), ctypes.byref(r), ctypes.byref(t)))
+        return {"two_step": bool(o.value), "tile_rows2": r.value, "tiles2": t.value}
+
     def tune(self, probe_steps=64, use_cache=True):
         """Run the library's autotuner (or reuse a cached choice for this batch
         signature and device). Returns the chosen schedule."""
@@ -185,17 +197,19 @@ class Batch:
                 cache = json.load(open(CACHE))
             except ValueError:
                 cache = {}
-        if use_cache and key in cache and "tile_rows" in cache[key] and "persistent" in cache[key]:
+        if use_cache and key in cache and all(k in cache[key] for k in ("tile_rows", "persistent", "two_step")):
             c = cache[key]
             self.set_schedule(c["region"], c["steps_per_launch"])
             self.set_persistent(c["persistent"])
             self.set_tile_rows(c["tile_rows"])
+            self.set_two_step(c["two_step"], c["tile_rows2"])
             return dict(c, cached=True)
         best = ctypes.c_double()
         _check(_lib().lbm_batch_tune(self.handle, int(probe_steps), ctypes.byref(best)))
         s = self.schedule()
         s.update(self.tile_rows())
         s["persistent"] = self.persistent()["persistent"]
+        s.update(self.two_step())
         s["probe_ms"] = best.value
         if use_cache:
             os.makedirs(os.path.dirname(CACHE), exist_ok=True)

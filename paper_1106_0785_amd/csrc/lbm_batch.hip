@@ -80,6 +80,11 @@ struct lbm_batch {
   int max_tiles;   // room in tile_inst (tiles at the smallest height)
   int tile_rows;   // rows per tile of the tiled instances
   int tbegin[4][3], tend[4][3];  // [version][variant: 0 plain, 1 NEQ walls, 2 flux-limited]
+  // two steps per launch for the plain tiled instances (k_batch_tiles2)
+  int pairs;        // 1: plain tiled instances advance two steps per launch
+  int* tile_inst2;  // two-step tile -> index in tinsts, grouped by version
+  int ntiles2, max_tiles2, tile_rows2;
+  int t2begin[4], t2end[4];
   int max_chunks;
   int* budget;
   int* flag;       // health flag (flag[0]), first of the STATUS_BYTES status words
@@ -88,14 +93,15 @@ struct lbm_batch {
   long long timeout_ticks;  // bound on one barrier wait, wall-clock ticks
   int resident[4][2];       // resident workgroups of the persistent kernel [version][region 128, 256]; 0 unknown
   int cur;   // current buffer of the line instances
-  int cur2;  // current buffer of the tiled instances
+  int cur2;  // current buffer of the tiled instances with walls or the flux-limited scheme
+  int cur3;  // current buffer of the plain tiled instances
   Schedule sched;
   int use_graph;
   // chunk ranges per equilibrium version (1..3): [begin, end)
   int vbegin[4], vend[4];
-  // cached graphs, one per (cur, cur2)
-  hipGraphExec_t graph[4];
-  int64_t graph_steps[4];
+  // cached graphs, one per (cur, cur2, cur3)
+  hipGraphExec_t graph[8];
+  int64_t graph_steps[8];
 };
 
 static long long line_len(const lbm_params& p) { return (long long)p.nx * p.ny; }
@@ -129,9 +135,9 @@ static int batch_tile_rows(const lbm_params* inst, int32_t n) {
 static int tile_variant(const lbm_params& p) { return p.scheme == 1 ? 2 : (has_walls(&p) ? 1 : 0); }
 
 struct Layout {
-  size_t arena_bytes, insts_off, chunks_off, tinsts_off, tiles_off, budget_off, flag_off, backup_off, total;
+  size_t arena_bytes, insts_off, chunks_off, tinsts_off, tiles_off, tiles2_off, budget_off, flag_off, backup_off, total;
   long long arena_doubles;
-  int max_chunks, ntiled, ntiles;  // ntiles: at the smallest tile height
+  int max_chunks, ntiled, ntiles, ntiles2;  // ntiles, ntiles2: at the smallest tile heights
   int rows;  // default rows per tile of the tiled instances
   std::vector<long long> off;  // arena offset (doubles) of each instance
 };
@@ -139,7 +145,7 @@ struct Layout {
 static lbm_status layout_of(const lbm_params* inst, int32_t n, Layout* L) {
   if (!inst || n < 1) return fail(LBM_EINVAL, "need at least one instance");
   long long dbl = 0, maxc = 0;
-  int ntiled = 0, ntiles = 0;
+  int ntiled = 0, ntiles = 0, ntiles2 = 0;
   L->off.assign(n, 0);
   for (int i = 0; i < n; ++i) {
     lbm_status st = validate(&inst[i]);
@@ -164,18 +170,25 @@ static lbm_status layout_of(const lbm_params* inst, int32_t n, Layout* L) {
       ++ntiled;
       if ((long long)ntiles + g.ntiles > INT_MAX / 2) return fail(LBM_EINVAL, "batch has too many tiles");
       ntiles += g.ntiles;
+      if (tile_variant(p) == 0) {
+        const March2Geom g2 = march2_geom(p.nx, p.ny, TileShape{2, 2});
+        if ((long long)ntiles2 + g2.ntiles > INT_MAX / 2) return fail(LBM_EINVAL, "batch has too many tiles");
+        ntiles2 += g2.ntiles;
+      }
     }
   }
   L->arena_doubles = dbl;
   L->max_chunks = (int)maxc;
   L->ntiled = ntiled;
   L->ntiles = ntiles;
+  L->ntiles2 = ntiles2;
   L->arena_bytes = align256((size_t)dbl * sizeof(double));
   L->insts_off = 2 * L->arena_bytes;
   L->chunks_off = L->insts_off + align256((size_t)n * sizeof(LineInst));
   L->tinsts_off = L->chunks_off + align256((size_t)std::max<long long>(maxc, 1) * sizeof(LineChunk));
   L->tiles_off = L->tinsts_off + align256((size_t)std::max(ntiled, 1) * sizeof(TileInst));
-  L->budget_off = L->tiles_off + align256((size_t)std::max(ntiles, 1) * sizeof(int));
+  L->tiles2_off = L->tiles_off + align256((size_t)std::max(ntiles, 1) * sizeof(int));
+  L->budget_off = L->tiles2_off + align256((size_t)std::max(ntiles2, 1) * sizeof(int));
   L->flag_off = L->budget_off + align256((size_t)n * sizeof(int));
   L->backup_off = L->flag_off + STATUS_BYTES;
   L->total = L->backup_off + L->arena_bytes;
@@ -183,7 +196,7 @@ static lbm_status layout_of(const lbm_params* inst, int32_t n, Layout* L) {
 }
 
 static void drop_graphs(lbm_batch* b) {
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < 8; ++k) {
     if (b->graph[k]) (void)hipGraphExecDestroy(b->graph[k]);
     b->graph[k] = nullptr;
     b->graph_steps[k] = -1;
@@ -256,6 +269,50 @@ static lbm_status build_tiles(lbm_batch* b, int rows) {
   return LBM_OK;
 }
 
+// Cuts the plain tiled instances into the two-step kernel's strips with
+// `rows` output rows per tile, builds their tile list grouped by equilibrium
+// version and uploads descriptors and list.
+static lbm_status build_tiles2(lbm_batch* b, int rows) {
+  std::vector<int> tiles;
+  for (TileInst& T : b->host_tinsts) T.geom2 = march2_geom(T.nx, T.ny, TileShape{rows, 2});
+  for (int ver = 1; ver <= 3; ++ver) {
+    b->t2begin[ver] = (int)tiles.size();
+    for (size_t j = 0; j < b->host_tinsts.size(); ++j) {
+      const lbm_params& p = b->params[b->host_tinsts[j].gidx];
+      if (p.eq_version != ver || tile_variant(p) != 0) continue;
+      b->host_tinsts[j].first_tile2 = (int)tiles.size() - b->t2begin[ver];
+      for (int t = 0; t < b->host_tinsts[j].geom2.ntiles; ++t) tiles.push_back((int)j);
+    }
+    b->t2end[ver] = (int)tiles.size();
+  }
+  if ((long long)tiles.size() > b->max_tiles2) return fail(LBM_EINVAL, "tile height needs more tiles than reserved");
+  hipError_t e = hipSuccess;
+  if (!b->host_tinsts.empty())
+    e = hipMemcpyAsync(b->tinsts, b->host_tinsts.data(), b->host_tinsts.size() * sizeof(TileInst),
+                       hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess && !tiles.empty())
+    e = hipMemcpyAsync(b->tile_inst2, tiles.data(), tiles.size() * sizeof(int), hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return hip_fail(e, "uploading the two-step tile list");
+  b->ntiles2 = (int)tiles.size();
+  b->tile_rows2 = rows;
+  drop_graphs(b);
+  return LBM_OK;
+}
+
+// Output rows per two-step tile: the tallest even height of 128, 64, ... 8
+// that still gives the plain tiled instances ~1024 tiles.
+static int batch_tile_rows2(const lbm_batch* b) {
+  int rows = 128;
+  for (; rows > 8; rows /= 2) {
+    long long tiles = 0;
+    for (const TileInst& T : b->host_tinsts)
+      if (tile_variant(b->params[T.gidx]) == 0) tiles += march2_geom(T.nx, T.ny, TileShape{rows, 2}).ntiles;
+    if (tiles >= 1024) break;
+  }
+  return rows;
+}
+
 // Workgroups of the persistent kernel of (version, region) resident on the
 // stream's device at once (all its compute units, the kernel alone).
 static hipError_t resident_workgroups(lbm_batch* b, int ver, int region, int* out) {
@@ -277,10 +334,14 @@ static hipError_t resident_workgroups(lbm_batch* b, int ver, int region, int* ou
 
 // Enqueues nsteps steps of every instance: the line instances as
 // ceil(nsteps / h) temporal-blocking launches starting from buffer
-// start_cur, the tiled instances as one launch per step and group starting
-// from buffer start_cur2; `what` selects lines (1), tiled instances (2) or both.
-static hipError_t enqueue_steps(lbm_batch* b, int64_t nsteps, int start_cur, int start_cur2, hipStream_t stream,
-                                int what = 3) {
+// start_cur; the tiled instances with walls or the flux-limited scheme as
+// one launch per step and group starting from buffer start_cur2; the plain
+// tiled instances from buffer start_cur3, one launch per step, or in pair
+// mode two launches (two-step tiles, then the one-step tiles for instances
+// with one step left) per pair of steps. `what` selects lines (1), tiled
+// instances (2) or both.
+static hipError_t enqueue_steps(lbm_batch* b, int64_t nsteps, int start_cur, int start_cur2, int start_cur3,
+                                hipStream_t stream, int what = 3) {
   int cur = start_cur;
   const bool lines = (what & 1) && b->vend[3] > b->vbegin[1];
   if (lines && b->persistent) {
@@ -327,27 +388,51 @@ static hipError_t enqueue_steps(lbm_batch* b, int64_t nsteps, int start_cur, int
     }
     cur ^= 1;
   }
-  int cur2 = start_cur2;
-  for (int64_t n = 0; (what & 2) && b->ntiles > 0 && n < nsteps; ++n) {
+  auto one_step_kernel = [](int ver, int w) {
+    if (w == 1) return ver == 2 ? k_batch_tiles<2, true, 1> : ver == 3 ? k_batch_tiles<3, true, 1> : k_batch_tiles<1, true, 1>;
+    if (w == 2)
+      return ver == 2 ? k_batch_tiles<2, false, 2> : ver == 3 ? k_batch_tiles<3, false, 2> : k_batch_tiles<1, false, 2>;
+    return ver == 2 ? k_batch_tiles<2, false, 1> : ver == 3 ? k_batch_tiles<3, false, 1> : k_batch_tiles<1, false, 1>;
+  };
+  auto launch_tiles = [&](int ver, int w, int c, int64_t n, int pairs) -> hipError_t {
+    const int nt = b->tend[ver][w] - b->tbegin[ver][w];
+    if (nt == 0) return hipSuccess;
+    const int per_xcd = (nt + 7) / 8;
+    hipLaunchKernelGGL(one_step_kernel(ver, w), dim3(8 * per_xcd), dim3(64 * WAVES), 0, stream, b->arena[c],
+                       b->arena[c ^ 1], b->tinsts, b->tile_inst + b->tbegin[ver][w], nt, per_xcd, b->budget, (int)n,
+                       (int)nsteps, pairs, b->flag);
+    return hipGetLastError();
+  };
+  const bool tiled = (what & 2) && b->ntiles > 0;
+  // tiled instances with walls or the flux-limited scheme, and the plain ones
+  // when not in pair mode: one launch per step and group
+  int cur2 = start_cur2, cur3 = start_cur3;
+  for (int64_t n = 0; tiled && n < nsteps; ++n) {
     for (int ver = 1; ver <= 3; ++ver)
       for (int w = 0; w < 3; ++w) {
-        const int nt = b->tend[ver][w] - b->tbegin[ver][w];
-        if (nt == 0) continue;
-        const int per_xcd = (nt + 7) / 8;
-        decltype(&k_batch_tiles<1, false, 1>) k;
-        if (w == 1)
-          k = ver == 2 ? k_batch_tiles<2, true, 1> : ver == 3 ? k_batch_tiles<3, true, 1> : k_batch_tiles<1, true, 1>;
-        else if (w == 2)
-          k = ver == 2 ? k_batch_tiles<2, false, 2> : ver == 3 ? k_batch_tiles<3, false, 2> : k_batch_tiles<1, false, 2>;
-        else
-          k = ver == 2 ? k_batch_tiles<2, false, 1> : ver == 3 ? k_batch_tiles<3, false, 1> : k_batch_tiles<1, false, 1>;
-        hipLaunchKernelGGL(k, dim3(8 * per_xcd), dim3(64 * WAVES), 0, stream, b->arena[cur2], b->arena[cur2 ^ 1],
-                           b->tinsts, b->tile_inst + b->tbegin[ver][w], nt, per_xcd, b->budget, (int)n, (int)nsteps,
-                           b->flag);
-        hipError_t e = hipGetLastError();
+        if (w == 0 && b->pairs) continue;
+        hipError_t e = launch_tiles(ver, w, w == 0 ? cur3 : cur2, n, 0);
         if (e != hipSuccess) return e;
       }
     cur2 ^= 1;
+    if (!b->pairs) cur3 ^= 1;
+  }
+  // pair mode: the plain tiled instances two steps per launch
+  for (int64_t n = 0; tiled && b->pairs && n < nsteps; n += 2) {
+    for (int ver = 1; ver <= 3; ++ver) {
+      const int nt = b->t2end[ver] - b->t2begin[ver];
+      if (nt > 0 && n + 1 < nsteps) {
+        const int per_xcd = (nt + 7) / 8;
+        auto k2 = ver == 2 ? k_batch_tiles2<2> : ver == 3 ? k_batch_tiles2<3> : k_batch_tiles2<1>;
+        hipLaunchKernelGGL(k2, dim3(8 * per_xcd), dim3(128), 0, stream, b->arena[cur3], b->arena[cur3 ^ 1], b->tinsts,
+                           b->tile_inst2 + b->t2begin[ver], nt, per_xcd, b->budget, (int)n, (int)nsteps, b->flag);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+      }
+      hipError_t e = launch_tiles(ver, 0, cur3, n, 1);
+      if (e != hipSuccess) return e;
+    }
+    cur3 ^= 1;
   }
   return hipSuccess;
 }
@@ -385,6 +470,7 @@ lbm_status lbm_batch_create(const lbm_params* inst, int32_t n, void* d_workspace
   b->chunks = (LineChunk*)(base + L.chunks_off);
   b->tinsts = (TileInst*)(base + L.tinsts_off);
   b->tile_inst = (int*)(base + L.tiles_off);
+  b->tile_inst2 = (int*)(base + L.tiles2_off);
   b->budget = (int*)(base + L.budget_off);
   b->flag = (int*)(base + L.flag_off);
   b->ctr = (unsigned long long*)(base + L.flag_off + 128);
@@ -396,10 +482,15 @@ lbm_status lbm_batch_create(const lbm_params* inst, int32_t n, void* d_workspace
   b->ntiles = 0;
   b->max_tiles = L.ntiles;
   b->tile_rows = 0;
+  b->ntiles2 = 0;
+  b->max_tiles2 = L.ntiles2;
+  b->tile_rows2 = 0;
+  b->pairs = 0;
   b->cur = 0;
   b->cur2 = 0;
+  b->cur3 = 0;
   b->use_graph = 1;
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < 8; ++k) {
     b->graph[k] = nullptr;
     b->graph_steps[k] = -1;
   }
@@ -463,6 +554,7 @@ lbm_status lbm_batch_create(const lbm_params* inst, int32_t n, void* d_workspace
   }
   st = build_chunks(b, Schedule{256, 16});
   if (st == LBM_OK) st = build_tiles(b, L.rows);
+  if (st == LBM_OK) st = build_tiles2(b, batch_tile_rows2(b));
   if (st != LBM_OK) {
     (void)hipStreamDestroy(b->capture);
     delete b;
@@ -502,7 +594,10 @@ static Field field_of(const lbm_batch* b, int i, int buf) {
 }
 
 // Buffer holding the current state of instance i.
-static int current_buf(const lbm_batch* b, int i) { return b->tiled[i] ? b->cur2 : b->cur; }
+static int current_buf(const lbm_batch* b, int i) {
+  if (!b->tiled[i]) return b->cur;
+  return tile_variant(b->params[i]) == 0 ? b->cur3 : b->cur2;
+}
 
 lbm_status lbm_batch_init(lbm_batch* b, const double* d_rho, const double* d_ux, const double* d_uy,
                           const double* d_T) {
@@ -522,6 +617,7 @@ lbm_status lbm_batch_init(lbm_batch* b, const double* d_rho, const double* d_ux,
   if (e != hipSuccess) return hip_fail(e, "k_init launch");
   b->cur = 0;
   b->cur2 = 0;
+  b->cur3 = 0;
   return LBM_OK;
 }
 
@@ -545,17 +641,17 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps) {
   if (nsteps == 0) return LBM_OK;
   const int L = launches_for(b, nsteps);
   if (!b->use_graph) {
-    hipError_t e = enqueue_steps(b, nsteps, b->cur, b->cur2, b->stream);
+    hipError_t e = enqueue_steps(b, nsteps, b->cur, b->cur2, b->cur3, b->stream);
     if (e != hipSuccess) return hip_fail(e, "batched step launch");
   } else {
-    const int c = b->cur + 2 * b->cur2;
+    const int c = b->cur + 2 * b->cur2 + 4 * b->cur3;
     if (b->graph_steps[c] != nsteps) {
       if (b->graph[c]) (void)hipGraphExecDestroy(b->graph[c]);
       b->graph[c] = nullptr;
       hipGraph_t g = nullptr;
       hipError_t e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal);
       if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-      e = enqueue_steps(b, nsteps, b->cur, b->cur2, b->capture);
+      e = enqueue_steps(b, nsteps, b->cur, b->cur2, b->cur3, b->capture);
       hipError_t e2 = hipStreamEndCapture(b->capture, &g);
       if ((e != hipSuccess || e2 != hipSuccess) && g) (void)hipGraphDestroy(g);
       if (e != hipSuccess) return hip_fail(e, "capturing the batched steps");
@@ -573,6 +669,7 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps) {
   }
   if (L & 1) b->cur ^= 1;
   if (nsteps & 1) b->cur2 ^= 1;
+  if ((b->pairs ? (nsteps + 1) / 2 : nsteps) & 1) b->cur3 ^= 1;
   return LBM_OK;
 }
 
@@ -695,9 +792,9 @@ lbm_status lbm_batch_tune(lbm_batch* b, int64_t probe_steps, double* best_ms) {
     if (build_chunks(b, tr.s) != LBM_OK) continue;
     b->persistent = tr.pers;
     // warm-up + timed trial, both without graphs
-    e = enqueue_steps(b, std::min<int64_t>(probe_steps, 2 * tr.s.h), b->cur, b->cur2, b->stream, 1);
+    e = enqueue_steps(b, std::min<int64_t>(probe_steps, 2 * tr.s.h), b->cur, b->cur2, b->cur3, b->stream, 1);
     if (e == hipSuccess) e = hipEventRecord(t0, b->stream);
-    if (e == hipSuccess) e = enqueue_steps(b, probe_steps, b->cur, b->cur2, b->stream, 1);
+    if (e == hipSuccess) e = enqueue_steps(b, probe_steps, b->cur, b->cur2, b->cur3, b->stream, 1);
     if (e == hipSuccess) e = hipEventRecord(t1, b->stream);
     if (e == hipSuccess) e = hipEventSynchronize(t1);
     if (e != hipSuccess) break;
@@ -730,8 +827,24 @@ lbm_status lbm_batch_tune(lbm_batch* b, int64_t probe_steps, double* best_ms) {
     if (best_ms) *best_ms = best_t;
     return LBM_OK;
   }
-  // tile height of the tiled instances, timed the same way on their state
+  // tile shapes of the tiled instances, timed the same way on their state:
+  // one step per launch at each tile height, then (with plain tiled
+  // instances) two steps per launch at each two-step tile height. First the
+  // plain instances' state is moved into the others' buffer, so that one
+  // arena holds the whole tiled state.
+  e = hipSuccess;
+  bool any_plain = false;
+  for (const TileInst& T : b->host_tinsts) {
+    if (tile_variant(b->params[T.gidx]) != 0) continue;
+    any_plain = true;
+    if (b->cur3 != b->cur2 && e == hipSuccess)
+      e = hipMemcpyAsync(b->arena[b->cur2] + T.off, b->arena[b->cur3] + T.off, (size_t)16 * T.plane * sizeof(double),
+                         hipMemcpyDeviceToDevice, b->stream);
+  }
+  if (e != hipSuccess) return hip_fail(e, "aligning the tiled state");
+  b->cur3 = b->cur2;
   const int saved_cur2 = b->cur2;
+  const int saved_pairs = b->pairs;
   t0 = t1 = nullptr;
   e = hipMemcpyAsync(b->backup, b->arena[saved_cur2], bytes, hipMemcpyDeviceToDevice, b->stream);
   if (e == hipSuccess) e = hipEventCreate(&t0);
@@ -740,36 +853,58 @@ lbm_status lbm_batch_tune(lbm_batch* b, int64_t probe_steps, double* best_ms) {
     if (t0) (void)hipEventDestroy(t0);
     return hip_fail(e, "backing up the state");
   }
-  int best_rows = b->tile_rows;
+  auto trial = [&](float* ms) -> hipError_t {
+    hipError_t r = enqueue_steps(b, 2, b->cur, saved_cur2, saved_cur2, b->stream, 2);
+    if (r == hipSuccess) r = hipEventRecord(t0, b->stream);
+    if (r == hipSuccess) r = enqueue_steps(b, probe_steps, b->cur, saved_cur2, saved_cur2, b->stream, 2);
+    if (r == hipSuccess) r = hipEventRecord(t1, b->stream);
+    if (r == hipSuccess) r = hipEventSynchronize(t1);
+    if (r == hipSuccess) r = hipEventElapsedTime(ms, t0, t1);
+    if (r == hipSuccess) r = hipMemcpyAsync(b->arena[saved_cur2], b->backup, bytes, hipMemcpyDeviceToDevice, b->stream);
+    return r;
+  };
+  int best_rows = b->tile_rows, best_rows2 = b->tile_rows2, best_pairs = 0;
   float best_tt = 1e30f;
   const int heights[5] = {8, 16, 32, 64, 128};
+  b->pairs = 0;
   for (int rows : heights) {
     if (build_tiles(b, rows) != LBM_OK) continue;
-    e = enqueue_steps(b, 2, saved_cur2, saved_cur2, b->stream, 2);
-    if (e == hipSuccess) e = hipEventRecord(t0, b->stream);
-    if (e == hipSuccess) e = enqueue_steps(b, probe_steps, saved_cur2, saved_cur2, b->stream, 2);
-    if (e == hipSuccess) e = hipEventRecord(t1, b->stream);
-    if (e == hipSuccess) e = hipEventSynchronize(t1);
-    if (e != hipSuccess) break;
     float ms = 0;
-    e = hipEventElapsedTime(&ms, t0, t1);
+    e = trial(&ms);
     if (e != hipSuccess) break;
     if (ms < best_tt) {
       best_tt = ms;
       best_rows = rows;
     }
-    e = hipMemcpyAsync(b->arena[saved_cur2], b->backup, bytes, hipMemcpyDeviceToDevice, b->stream);
-    if (e != hipSuccess) break;
+  }
+  if (e == hipSuccess && any_plain && build_tiles(b, best_rows) == LBM_OK) {
+    b->pairs = 1;
+    for (int rows : heights) {
+      if (build_tiles2(b, rows) != LBM_OK) continue;
+      float ms = 0;
+      e = trial(&ms);
+      if (e != hipSuccess) break;
+      if (ms < best_tt) {
+        best_tt = ms;
+        best_rows2 = rows;
+        best_pairs = 1;
+      }
+    }
   }
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
+  b->pairs = saved_pairs;
   if (e == hipSuccess) e = hipMemcpyAsync(b->arena[saved_cur2], b->backup, bytes, hipMemcpyDeviceToDevice, b->stream);
   if (e == hipSuccess) e = hipMemsetAsync(b->flag, 0, sizeof(int), b->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) return hip_fail(e, "tuning run");
   b->cur2 = saved_cur2;
+  b->cur3 = saved_cur2;
   if (best_ms) *best_ms = best_t + best_tt;
-  return build_tiles(b, best_rows);
+  lbm_status st2 = build_tiles(b, best_rows);
+  if (st2 == LBM_OK) st2 = build_tiles2(b, best_rows2);
+  if (st2 == LBM_OK) b->pairs = best_pairs;
+  return st2;
 }
 
 lbm_status lbm_batch_set_tile_rows(lbm_batch* b, int32_t rows) {
@@ -777,6 +912,24 @@ lbm_status lbm_batch_set_tile_rows(lbm_batch* b, int32_t rows) {
   if (rows < WAVES || rows > 4096 || rows % WAVES)
     return fail(LBM_EINVAL, "tile rows must be a multiple of %d in [%d, 4096]", WAVES, WAVES);
   return build_tiles(b, rows);
+}
+
+lbm_status lbm_batch_set_two_step(lbm_batch* b, int32_t on, int32_t rows) {
+  if (!b) return fail(LBM_EINVAL, "batch is NULL");
+  if (on != 0 && on != 1) return fail(LBM_EINVAL, "on must be 0 or 1");
+  if (rows < 2 || rows > 4096 || rows % 2) return fail(LBM_EINVAL, "two-step tile rows must be even, in [2, 4096]");
+  lbm_status st = build_tiles2(b, rows);
+  if (st != LBM_OK) return st;
+  b->pairs = on;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_get_two_step(const lbm_batch* b, int32_t* on, int32_t* rows, int32_t* ntiles) {
+  if (!b) return fail(LBM_EINVAL, "batch is NULL");
+  if (on) *on = b->pairs;
+  if (rows) *rows = b->tile_rows2;
+  if (ntiles) *ntiles = b->ntiles2;
+  return LBM_OK;
 }
 
 lbm_status lbm_batch_get_tile_rows(const lbm_batch* b, int32_t* rows, int32_t* ntiles) {

@@ -8,6 +8,7 @@
 // Each node update is the same arithmetic as the single-problem kernels.
 #pragma once
 
+#include "lbm_fused2.h"
 #include "lbm_kernels.h"
 
 namespace lbm {
@@ -332,7 +333,10 @@ struct TileInst {
   int nx, ny;
   int gidx;          // index of the instance in the batch (budgets)
   int first_tile;    // index of its first tile in the batch's tile list
+  int first_tile2;   // ... in the two-step tile list (plain instances)
+  int pad;
   MarchGeom geom;
+  March2Geom geom2;  // its strips of the two-step kernel
   Hot hot;
   Cold cold;
 };
@@ -341,16 +345,25 @@ struct TileInst {
 // equilibrium version and variant: NEQ walls, or the flux-limited scheme
 // with its radius-2 stencil HR = 2); workgroup b takes tile
 // (b mod 8) per_xcd + b / 8 of the group's list, so each XCD gets a
-// contiguous run. An instance whose budget b is spent (step n >= b of a call
-// of nsteps steps) idles: its final state stays where step b - 1 put it, and
-// at n == b it is copied across once if the remaining nsteps - b steps are
-// odd, so that after the call it sits in the same buffer as everyone else's.
+// contiguous run.
+//
+// Budgets, one launch per step (pairs = 0): an instance whose budget b is
+// spent (step n >= b of a call of nsteps steps) idles: its final state stays
+// where step b - 1 put it, and at n == b it is copied across once if the
+// remaining nsteps - b steps are odd, so that after the call it sits in the
+// same buffer as everyone else's.
+// Pairs of steps (pairs = 1, plain instances beside k_batch_tiles2): the
+// launch for steps (n, n + 1) does the step only for an instance with just
+// one step left (n + 1 == m, m = min(b, nsteps)); one with two left is
+// k_batch_tiles2's; an idle one (n >= m) is copied across once, at the first
+// pair after its last, if the pairs left in the call are odd (every active
+// pair moves the state to the other buffer once).
 template <int VER, bool WALLS, int HR>
 __global__ __launch_bounds__(64 * WAVES, 2) void k_batch_tiles(const double* __restrict__ A, double* __restrict__ B,
                                                                 const TileInst* __restrict__ insts,
                                                                 const int* __restrict__ tile_inst, int ntiles,
                                                                 int per_xcd, const int* __restrict__ budget, int n,
-                                                                int nsteps, int* flag) {
+                                                                int nsteps, int pairs, int* flag) {
   const int t = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
   if (t >= ntiles) return;  // whole workgroup leaves together
   const TileInst& I = insts[tile_inst[t]];
@@ -363,8 +376,22 @@ __global__ __launch_bounds__(64 * WAVES, 2) void k_batch_tiles(const double* __r
   F.plane = I.plane;
   const int tile = t - I.first_tile;
   const int bud = budget[I.gidx];
-  if (bud <= n) {
-    if (n != bud || ((nsteps - bud) & 1) == 0) return;
+  bool copy;
+  if (pairs) {
+    const int m = min(bud, nsteps);
+    if (n + 2 <= m) return;  // two steps: the two-step kernel's
+    if (n + 1 == m) {
+      copy = false;
+    } else {
+      const int done = (m + 1) / 2, total = (nsteps + 1) / 2;  // pairs active, pairs in the call
+      if (n != 2 * done || ((total - done) & 1) == 0) return;
+      copy = true;
+    }
+  } else {
+    copy = bud <= n;
+    if (copy && (n != bud || ((nsteps - bud) & 1) == 0)) return;
+  }
+  if (copy) {
     const int strip = tile % I.geom.nstrips, seg = tile / I.geom.nstrips;
     const int x = strip * STRIP + (threadIdx.x & 63);
     const int y1 = min((seg + 1) * I.geom.rows, I.ny);
@@ -374,6 +401,29 @@ __global__ __launch_bounds__(64 * WAVES, 2) void k_batch_tiles(const double* __r
     return;
   }
   fused_tile<VER, WALLS, WAVES, HR>(F, &I.hot, &I.cold, I.geom, tile, flag);
+}
+
+// Steps (n, n + 1) of every two-step tile (`geom2`) of the plain instances
+// of one equilibrium version that have both steps left in the call; the
+// others are k_batch_tiles's (pairs = 1). Each instance's two steps are
+// those of k_step_fused2 on it alone.
+template <int VER>
+__global__ __launch_bounds__(128, 1) void k_batch_tiles2(const double* __restrict__ A, double* __restrict__ B,
+                                                         const TileInst* __restrict__ insts,
+                                                         const int* __restrict__ tile_inst, int ntiles, int per_xcd,
+                                                         const int* __restrict__ budget, int n, int nsteps, int* flag) {
+  const int t = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (t >= ntiles) return;  // whole workgroup leaves together
+  const TileInst& I = insts[tile_inst[t]];
+  if (min(budget[I.gidx], nsteps) < n + 2) return;
+  Field F;
+  F.fin = A + I.off;
+  F.fout = B + I.off;
+  F.nx = I.nx;
+  F.ny = I.ny;
+  F.pitch = I.pitch;
+  F.plane = I.plane;
+  fused2_tile<VER, 2, true>(F, &I.hot, &I.cold, I.geom2, t - I.first_tile2, flag);
 }
 
 }  // namespace lbm

@@ -200,7 +200,10 @@ def test_mixed_tuner_keeps_state():
     assert np.array_equal(f0, f1), s
     b.step(5)
     items2, r = _mixed(11, 12)
-    r.step(22)
+    r.step(17)
+    t = b.two_step()
+    r.set_two_step(t["two_step"], t["tile_rows2"])  # the plain 2-D instances as the tuner left them
+    r.step(5)
     assert np.array_equal(b.get_f().cpu().numpy(), r.get_f().cpu().numpy())
     b.close()
     r.close()
