@@ -75,16 +75,18 @@ struct lbm_batch {
   LineInst* insts;
   LineChunk* chunks;
   TileInst* tinsts;
-  int* tile_inst;  // tile -> index in tinsts, grouped by (version, walls)
-  int ntiles;      // tiles at the current tile height
-  int max_tiles;   // room in tile_inst (tiles at the smallest height)
-  int tile_rows;   // rows per tile of the tiled instances
-  int tbegin[4][3], tend[4][3];  // [version][variant: 0 plain, 1 NEQ walls, 2 flux-limited]
+  int2* tile_inst;  // tile list entries (index in tinsts, tile of the instance), grouped by (version, variant)
+  int ntiles;       // tiles at the current tile height
+  int max_tiles;    // room in tile_inst (tiles at the smallest height, padding included)
+  int tile_rows;    // rows per tile of the tiled instances
+  int tbegin[4][3], tend[4][3];  // entries of each [version][variant: 0 plain, 1 NEQ walls, 2 flux-limited]
+                                 // (a multiple of 8, padding included)
   // two steps per launch for the plain tiled instances (k_batch_tiles2)
   int pairs;        // 1: plain tiled instances advance two steps per launch
-  int* tile_inst2;  // two-step tile -> index in tinsts, grouped by version
+  int2* tile_inst2;  // two-step tile list entries (index in tinsts, tile of the instance), grouped by version
   int ntiles2, max_tiles2, tile_rows2;
-  int t2begin[4], t2end[4];
+  int t2begin[4], t2end[4];  // entries of each version (a multiple of 8, padding included)
+  std::vector<int> host_budget;
   int max_chunks;
   int* budget;
   int* flag;       // health flag (flag[0]), first of the STATUS_BYTES status words
@@ -187,8 +189,8 @@ static lbm_status layout_of(const lbm_params* inst, int32_t n, Layout* L) {
   L->chunks_off = L->insts_off + align256((size_t)n * sizeof(LineInst));
   L->tinsts_off = L->chunks_off + align256((size_t)std::max<long long>(maxc, 1) * sizeof(LineChunk));
   L->tiles_off = L->tinsts_off + align256((size_t)std::max(ntiled, 1) * sizeof(TileInst));
-  L->tiles2_off = L->tiles_off + align256((size_t)std::max(ntiles, 1) * sizeof(int));
-  L->budget_off = L->tiles2_off + align256((size_t)std::max(ntiles2, 1) * sizeof(int));
+  L->tiles2_off = L->tiles_off + align256((size_t)(ntiles + 72 + 1) * sizeof(int2));
+  L->budget_off = L->tiles2_off + align256((size_t)(ntiles2 + 24 + 1) * sizeof(int2));
   L->flag_off = L->budget_off + align256((size_t)n * sizeof(int));
   L->backup_off = L->flag_off + STATUS_BYTES;
   L->total = L->backup_off + L->arena_bytes;
@@ -238,32 +240,56 @@ static lbm_status build_chunks(lbm_batch* b, const Schedule& s) {
   return LBM_OK;
 }
 
+// Appends one launch group's tiles to a tile list: (instance, tile) entries
+// with the height each tile owns, ordered by decreasing height and dealt
+// round-robin to the eight per-XCD runs the kernels' block mapping reads
+// (entry (b mod 8) per_xcd + b / 8 for workgroup b), so that every XCD
+// starts with its tallest tiles and the short tops of instances fill the
+// tail; padding entries (-1) fill the group to a multiple of 8. Returns the
+// number of real tiles.
+static long long append_group(std::vector<int2>& list, const std::vector<int2>& v, const std::vector<int>& h) {
+  std::vector<int> order(v.size());
+  for (size_t k = 0; k < order.size(); ++k) order[k] = (int)k;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return h[x] > h[y]; });
+  const size_t per_xcd = (v.size() + 7) / 8, begin = list.size();
+  list.resize(begin + 8 * per_xcd, int2{-1, 0});
+  for (size_t k = 0; k < order.size(); ++k) list[begin + (k % 8) * per_xcd + k / 8] = v[order[k]];
+  return (long long)v.size();
+}
+
 // Cuts the tiled instances into tiles of `rows` rows, builds the tile list
-// grouped by (equilibrium version, wall variant) and uploads descriptors and list.
+// grouped by (equilibrium version, variant) and uploads descriptors and list.
 static lbm_status build_tiles(lbm_batch* b, int rows) {
-  std::vector<int> tiles;
+  std::vector<int2> list;
+  long long real = 0;
   for (TileInst& T : b->host_tinsts) T.geom = march_geom(T.nx, T.ny, TileShape{rows, WAVES});
   for (int ver = 1; ver <= 3; ++ver)
     for (int w = 0; w < 3; ++w) {
-      b->tbegin[ver][w] = (int)tiles.size();
+      std::vector<int2> v;
+      std::vector<int> h;
       for (size_t j = 0; j < b->host_tinsts.size(); ++j) {
-        const lbm_params& p = b->params[b->host_tinsts[j].gidx];
+        const TileInst& T = b->host_tinsts[j];
+        const lbm_params& p = b->params[T.gidx];
         if (p.eq_version != ver || tile_variant(p) != w) continue;
-        b->host_tinsts[j].first_tile = (int)tiles.size() - b->tbegin[ver][w];
-        for (int t = 0; t < b->host_tinsts[j].geom.ntiles; ++t) tiles.push_back((int)j);
+        for (int t = 0; t < T.geom.ntiles; ++t) {
+          v.push_back(int2{(int)j, t});
+          h.push_back(std::min(T.geom.rows, T.ny - (t / T.geom.nstrips) * T.geom.rows));
+        }
       }
-      b->tend[ver][w] = (int)tiles.size();
+      b->tbegin[ver][w] = (int)list.size();
+      real += append_group(list, v, h);
+      b->tend[ver][w] = (int)list.size();
     }
-  if ((long long)tiles.size() > b->max_tiles) return fail(LBM_EINVAL, "tile height needs more tiles than reserved");
+  if ((long long)list.size() > b->max_tiles) return fail(LBM_EINVAL, "tile height needs more tiles than reserved");
   hipError_t e = hipSuccess;
   if (!b->host_tinsts.empty())
     e = hipMemcpyAsync(b->tinsts, b->host_tinsts.data(), b->host_tinsts.size() * sizeof(TileInst),
                        hipMemcpyHostToDevice, b->stream);
-  if (e == hipSuccess && !tiles.empty())
-    e = hipMemcpyAsync(b->tile_inst, tiles.data(), tiles.size() * sizeof(int), hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess && !list.empty())
+    e = hipMemcpyAsync(b->tile_inst, list.data(), list.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);  // the host vectors are the copy sources
   if (e != hipSuccess) return hip_fail(e, "uploading the tile list");
-  b->ntiles = (int)tiles.size();
+  b->ntiles = (int)real;
   b->tile_rows = rows;
   drop_graphs(b);
   return LBM_OK;
@@ -271,30 +297,37 @@ static lbm_status build_tiles(lbm_batch* b, int rows) {
 
 // Cuts the plain tiled instances into the two-step kernel's strips with
 // `rows` output rows per tile, builds their tile list grouped by equilibrium
-// version and uploads descriptors and list.
+// version (ordered as append_group orders) and uploads descriptors and list.
 static lbm_status build_tiles2(lbm_batch* b, int rows) {
-  std::vector<int> tiles;
+  std::vector<int2> list;
+  long long real = 0;
   for (TileInst& T : b->host_tinsts) T.geom2 = march2_geom(T.nx, T.ny, TileShape{rows, 2});
   for (int ver = 1; ver <= 3; ++ver) {
-    b->t2begin[ver] = (int)tiles.size();
+    std::vector<int2> v;
+    std::vector<int> h;
     for (size_t j = 0; j < b->host_tinsts.size(); ++j) {
-      const lbm_params& p = b->params[b->host_tinsts[j].gidx];
+      const TileInst& T = b->host_tinsts[j];
+      const lbm_params& p = b->params[T.gidx];
       if (p.eq_version != ver || tile_variant(p) != 0) continue;
-      b->host_tinsts[j].first_tile2 = (int)tiles.size() - b->t2begin[ver];
-      for (int t = 0; t < b->host_tinsts[j].geom2.ntiles; ++t) tiles.push_back((int)j);
+      for (int t = 0; t < T.geom2.ntiles; ++t) {
+        v.push_back(int2{(int)j, t});
+        h.push_back(std::min(T.geom2.rows, T.ny - (t / T.geom2.nstrips) * T.geom2.rows));
+      }
     }
-    b->t2end[ver] = (int)tiles.size();
+    b->t2begin[ver] = (int)list.size();
+    real += append_group(list, v, h);
+    b->t2end[ver] = (int)list.size();
   }
-  if ((long long)tiles.size() > b->max_tiles2) return fail(LBM_EINVAL, "tile height needs more tiles than reserved");
+  if ((long long)list.size() > b->max_tiles2) return fail(LBM_EINVAL, "tile height needs more tiles than reserved");
   hipError_t e = hipSuccess;
   if (!b->host_tinsts.empty())
     e = hipMemcpyAsync(b->tinsts, b->host_tinsts.data(), b->host_tinsts.size() * sizeof(TileInst),
                        hipMemcpyHostToDevice, b->stream);
-  if (e == hipSuccess && !tiles.empty())
-    e = hipMemcpyAsync(b->tile_inst2, tiles.data(), tiles.size() * sizeof(int), hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess && !list.empty())
+    e = hipMemcpyAsync(b->tile_inst2, list.data(), list.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) return hip_fail(e, "uploading the two-step tile list");
-  b->ntiles2 = (int)tiles.size();
+  b->ntiles2 = (int)real;
   b->tile_rows2 = rows;
   drop_graphs(b);
   return LBM_OK;
@@ -395,11 +428,11 @@ static hipError_t enqueue_steps(lbm_batch* b, int64_t nsteps, int start_cur, int
     return ver == 2 ? k_batch_tiles<2, false, 1> : ver == 3 ? k_batch_tiles<3, false, 1> : k_batch_tiles<1, false, 1>;
   };
   auto launch_tiles = [&](int ver, int w, int c, int64_t n, int pairs) -> hipError_t {
-    const int nt = b->tend[ver][w] - b->tbegin[ver][w];
-    if (nt == 0) return hipSuccess;
-    const int per_xcd = (nt + 7) / 8;
+    const int entries = b->tend[ver][w] - b->tbegin[ver][w];
+    if (entries == 0) return hipSuccess;
+    const int per_xcd = entries / 8;
     hipLaunchKernelGGL(one_step_kernel(ver, w), dim3(8 * per_xcd), dim3(64 * WAVES), 0, stream, b->arena[c],
-                       b->arena[c ^ 1], b->tinsts, b->tile_inst + b->tbegin[ver][w], nt, per_xcd, b->budget, (int)n,
+                       b->arena[c ^ 1], b->tinsts, b->tile_inst + b->tbegin[ver][w], per_xcd, b->budget, (int)n,
                        (int)nsteps, pairs, b->flag);
     return hipGetLastError();
   };
@@ -417,20 +450,33 @@ static hipError_t enqueue_steps(lbm_batch* b, int64_t nsteps, int start_cur, int
     cur2 ^= 1;
     if (!b->pairs) cur3 ^= 1;
   }
-  // pair mode: the plain tiled instances two steps per launch
+  // pair mode: the plain tiled instances two steps per launch. The budgets
+  // are known here, so a launch with nothing to do is left out (a change of
+  // budgets drops the cached graphs).
   for (int64_t n = 0; tiled && b->pairs && n < nsteps; n += 2) {
     for (int ver = 1; ver <= 3; ++ver) {
-      const int nt = b->t2end[ver] - b->t2begin[ver];
-      if (nt > 0 && n + 1 < nsteps) {
-        const int per_xcd = (nt + 7) / 8;
+      bool two = false, one = false;
+      for (const TileInst& T : b->host_tinsts) {
+        const lbm_params& p = b->params[T.gidx];
+        if (p.eq_version != ver || tile_variant(p) != 0) continue;
+        const int64_t m = std::min<int64_t>(b->host_budget[T.gidx], nsteps);
+        const int64_t done = (m + 1) / 2, total = (nsteps + 1) / 2;
+        if (n + 2 <= m) two = true;
+        else if (n + 1 == m || (n == 2 * done && ((total - done) & 1))) one = true;
+      }
+      const int entries = b->t2end[ver] - b->t2begin[ver];
+      if (two && entries > 0) {
+        const int per_xcd = entries / 8;
         auto k2 = ver == 2 ? k_batch_tiles2<2> : ver == 3 ? k_batch_tiles2<3> : k_batch_tiles2<1>;
         hipLaunchKernelGGL(k2, dim3(8 * per_xcd), dim3(128), 0, stream, b->arena[cur3], b->arena[cur3 ^ 1], b->tinsts,
-                           b->tile_inst2 + b->t2begin[ver], nt, per_xcd, b->budget, (int)n, (int)nsteps, b->flag);
+                           b->tile_inst2 + b->t2begin[ver], per_xcd, b->budget, (int)n, (int)nsteps, b->flag);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
       }
-      hipError_t e = launch_tiles(ver, 0, cur3, n, 1);
-      if (e != hipSuccess) return e;
+      if (one) {
+        hipError_t e = launch_tiles(ver, 0, cur3, n, 1);
+        if (e != hipSuccess) return e;
+      }
     }
     cur3 ^= 1;
   }
@@ -469,8 +515,8 @@ lbm_status lbm_batch_create(const lbm_params* inst, int32_t n, void* d_workspace
   b->insts = (LineInst*)(base + L.insts_off);
   b->chunks = (LineChunk*)(base + L.chunks_off);
   b->tinsts = (TileInst*)(base + L.tinsts_off);
-  b->tile_inst = (int*)(base + L.tiles_off);
-  b->tile_inst2 = (int*)(base + L.tiles2_off);
+  b->tile_inst = (int2*)(base + L.tiles_off);
+  b->tile_inst2 = (int2*)(base + L.tiles2_off);
   b->budget = (int*)(base + L.budget_off);
   b->flag = (int*)(base + L.flag_off);
   b->ctr = (unsigned long long*)(base + L.flag_off + 128);
@@ -480,10 +526,11 @@ lbm_status lbm_batch_create(const lbm_params* inst, int32_t n, void* d_workspace
   b->max_chunks = L.max_chunks;
   b->arena_doubles = L.arena_doubles;
   b->ntiles = 0;
-  b->max_tiles = L.ntiles;
+  b->max_tiles = L.ntiles + 72;
   b->tile_rows = 0;
   b->ntiles2 = 0;
-  b->max_tiles2 = L.ntiles2;
+  b->max_tiles2 = L.ntiles2 + 24;
+  b->host_budget.assign(n, INT_MAX);
   b->tile_rows2 = 0;
   b->pairs = 0;
   b->cur = 0;
@@ -632,6 +679,8 @@ lbm_status lbm_batch_set_budgets(lbm_batch* b, const int64_t* steps) {
   hipError_t e = hipMemcpyAsync(b->budget, budget.data(), b->n * sizeof(int), hipMemcpyHostToDevice, b->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) return hip_fail(e, "uploading budgets");
+  b->host_budget = budget;
+  drop_graphs(b);  // the pair-mode launches depend on the budgets
   return LBM_OK;
 }
 
@@ -788,7 +837,9 @@ lbm_status lbm_batch_tune(lbm_batch* b, int64_t probe_steps, double* best_ms) {
     for (int h : hs)
       for (int pers = 0; pers < 2; ++pers)
         if (schedule_ok(Schedule{r, h})) trials.push_back(Trial{Schedule{r, h}, pers});
+  const bool any_line = b->vend[3] > b->vbegin[1];
   for (const Trial& tr : trials) {
+    if (!any_line) break;  // no line instances: nothing to choose
     if (build_chunks(b, tr.s) != LBM_OK) continue;
     b->persistent = tr.pers;
     // warm-up + timed trial, both without graphs
@@ -812,6 +863,7 @@ lbm_status lbm_batch_tune(lbm_batch* b, int64_t probe_steps, double* best_ms) {
   }
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
+  if (!any_line) best_t = 0.0f;
   if (e == hipSuccess) e = hipMemcpyAsync(b->arena[saved_cur], b->backup, bytes, hipMemcpyDeviceToDevice, b->stream);
   int word[17] = {0};  // a timed-out barrier in a trial voids the persistent form
   if (e == hipSuccess) e = hipMemcpyAsync(word, b->flag, sizeof(word), hipMemcpyDeviceToHost, b->stream);
@@ -879,7 +931,8 @@ lbm_status lbm_batch_tune(lbm_batch* b, int64_t probe_steps, double* best_ms) {
   }
   if (e == hipSuccess && any_plain && build_tiles(b, best_rows) == LBM_OK) {
     b->pairs = 1;
-    for (int rows : heights) {
+    const int heights2[7] = {8, 16, 24, 32, 48, 64, 128};
+    for (int rows : heights2) {
       if (build_tiles2(b, rows) != LBM_OK) continue;
       float ms = 0;
       e = trial(&ms);

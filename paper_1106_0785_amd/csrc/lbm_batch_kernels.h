@@ -332,8 +332,6 @@ struct TileInst {
   long long pitch, plane;
   int nx, ny;
   int gidx;          // index of the instance in the batch (budgets)
-  int first_tile;    // index of its first tile in the batch's tile list
-  int first_tile2;   // ... in the two-step tile list (plain instances)
   int pad;
   MarchGeom geom;
   March2Geom geom2;  // its strips of the two-step kernel
@@ -343,9 +341,10 @@ struct TileInst {
 
 // One time step of every tile of a group of tile instances (same
 // equilibrium version and variant: NEQ walls, or the flux-limited scheme
-// with its radius-2 stencil HR = 2); workgroup b takes tile
-// (b mod 8) per_xcd + b / 8 of the group's list, so each XCD gets a
-// contiguous run.
+// with its radius-2 stencil HR = 2); workgroup b takes entry
+// (b mod 8) per_xcd + b / 8 of the group's list, (instance, tile of the
+// instance) or instance -1 for a padding entry, so each XCD gets a run of
+// its own.
 //
 // Budgets, one launch per step (pairs = 0): an instance whose budget b is
 // spent (step n >= b of a call of nsteps steps) idles: its final state stays
@@ -361,12 +360,12 @@ struct TileInst {
 template <int VER, bool WALLS, int HR>
 __global__ __launch_bounds__(64 * WAVES, 2) void k_batch_tiles(const double* __restrict__ A, double* __restrict__ B,
                                                                 const TileInst* __restrict__ insts,
-                                                                const int* __restrict__ tile_inst, int ntiles,
-                                                                int per_xcd, const int* __restrict__ budget, int n,
-                                                                int nsteps, int pairs, int* flag) {
-  const int t = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-  if (t >= ntiles) return;  // whole workgroup leaves together
-  const TileInst& I = insts[tile_inst[t]];
+                                                                const int2* __restrict__ tiles, int per_xcd,
+                                                                const int* __restrict__ budget, int n, int nsteps,
+                                                                int pairs, int* flag) {
+  const int2 en = tiles[(blockIdx.x % 8) * per_xcd + blockIdx.x / 8];
+  if (en.x < 0) return;  // whole workgroup leaves together
+  const TileInst& I = insts[en.x];
   Field F;
   F.fin = A + I.off;
   F.fout = B + I.off;
@@ -374,7 +373,7 @@ __global__ __launch_bounds__(64 * WAVES, 2) void k_batch_tiles(const double* __r
   F.ny = I.ny;
   F.pitch = I.pitch;
   F.plane = I.plane;
-  const int tile = t - I.first_tile;
+  const int tile = en.y;
   const int bud = budget[I.gidx];
   bool copy;
   if (pairs) {
@@ -406,15 +405,17 @@ __global__ __launch_bounds__(64 * WAVES, 2) void k_batch_tiles(const double* __r
 // Steps (n, n + 1) of every two-step tile (`geom2`) of the plain instances
 // of one equilibrium version that have both steps left in the call; the
 // others are k_batch_tiles's (pairs = 1). Each instance's two steps are
-// those of k_step_fused2 on it alone.
+// those of k_step_fused2 on it alone. Workgroup b takes entry
+// (b mod 8) per_xcd + b / 8 of the list: (instance, tile of the instance),
+// or instance -1 for a padding entry.
 template <int VER>
 __global__ __launch_bounds__(128, 1) void k_batch_tiles2(const double* __restrict__ A, double* __restrict__ B,
                                                          const TileInst* __restrict__ insts,
-                                                         const int* __restrict__ tile_inst, int ntiles, int per_xcd,
+                                                         const int2* __restrict__ tiles, int per_xcd,
                                                          const int* __restrict__ budget, int n, int nsteps, int* flag) {
-  const int t = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-  if (t >= ntiles) return;  // whole workgroup leaves together
-  const TileInst& I = insts[tile_inst[t]];
+  const int2 e = tiles[(blockIdx.x % 8) * per_xcd + blockIdx.x / 8];
+  if (e.x < 0) return;  // whole workgroup leaves together
+  const TileInst& I = insts[e.x];
   if (min(budget[I.gidx], nsteps) < n + 2) return;
   Field F;
   F.fin = A + I.off;
@@ -423,7 +424,7 @@ __global__ __launch_bounds__(128, 1) void k_batch_tiles2(const double* __restric
   F.ny = I.ny;
   F.pitch = I.pitch;
   F.plane = I.plane;
-  fused2_tile<VER, 2, true>(F, &I.hot, &I.cold, I.geom2, t - I.first_tile2, flag);
+  fused2_tile<VER, 2, true>(F, &I.hot, &I.cold, I.geom2, e.y, flag);
 }
 
 }  // namespace lbm
