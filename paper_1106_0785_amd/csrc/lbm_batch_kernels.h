@@ -137,10 +137,10 @@ __device__ __forceinline__ bool line_chunk(const double* __restrict__ A, double*
       double out[16];
       if (I.axis == 0) {
         nv = NbrVel{uxp, uyp, uxm, uym, ux0, uy0, ux0, uy0};
-        ok &= node_update<VER>(c, f, fp, fm, f, f, nv, out);
+        ok &= node_update_line<VER, 0>(c, f, fp, fm, nv, out);
       } else {
         nv = NbrVel{ux0, uy0, ux0, uy0, uxp, uyp, uxm, uym};
-        ok &= node_update<VER>(c, f, f, f, fp, fm, nv, out);
+        ok &= node_update_line<VER, 1>(c, f, fp, fm, nv, out);
       }
       double ux, uy;
       velocity_of(out, ux, uy);

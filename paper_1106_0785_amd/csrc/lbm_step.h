@@ -127,6 +127,32 @@ struct ConvAll<16> {
                          double*) {}
 };
 
+// The Lax-Wendroff increment of velocity I along one axis only (AXIS 0: x,
+// 1: y), for a node whose neighbours along the other axis are itself (a
+// one-dimensional problem: those terms are exact zeros, left out).
+template <int I, int AXIS>
+LBM_HD double convect_axis(const Hot& c, double f, double fp, double fm) {
+  constexpr int v = AXIS == 0 ? VX[I] : VY[I];
+  const double* l = AXIS == 0 ? c.lx : c.ly;
+  if (v == 1) return l[0] * (fp - f) + l[1] * (fm - f);
+  if (v == -1) return l[1] * (fp - f) + l[0] * (fm - f);
+  if (v == 2) return l[2] * (fp - f) + l[3] * (fm - f);
+  if (v == -2) return l[3] * (fp - f) + l[2] * (fm - f);
+  return 0.0;
+}
+
+template <int I, int AXIS>
+struct ConvAxis {
+  LBM_HD static void run(const Hot& c, const double* f, const double* fp, const double* fm, double* out) {
+    out[I] = convect_axis<I, AXIS>(c, f[I], fp[I], fm[I]);
+    ConvAxis<I + 1, AXIS>::run(c, f, fp, fm, out);
+  }
+};
+template <int AXIS>
+struct ConvAxis<16, AXIS> {
+  LBM_HD static void run(const Hot&, const double*, const double*, const double*, double*) {}
+};
+
 // Collision of one node in velocity space, -dt M^-1 Q (Sec. II), into df.
 // Returns false when rho <= 0, T <= 0 or a NaN appears.
 template <int VER>
@@ -171,6 +197,16 @@ template <int VER>
 LBM_HD bool node_update(const Hot& c, const double* f, const double* fxp, const double* fxm, const double* fyp,
                         const double* fym, const NbrVel& nv, double* out) {
   ConvAll<0>::run(c, f, fxp, fxm, fyp, fym, out);
+  return collide_add<VER>(c, f, nv, out);
+}
+
+// New distributions at a node of a one-dimensional problem along AXIS,
+// neighbours fp (+1) and fm (-1) along it: node_update with the other
+// axis's (zero) convection terms left out.
+template <int VER, int AXIS>
+LBM_HD bool node_update_line(const Hot& c, const double* f, const double* fp, const double* fm, const NbrVel& nv,
+                             double* out) {
+  ConvAxis<0, AXIS>::run(c, f, fp, fm, out);
   return collide_add<VER>(c, f, nv, out);
 }
 
