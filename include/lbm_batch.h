@@ -20,8 +20,10 @@
  * (lbm_batch_set_two_step) the plain ones (Lax-Wendroff, no NEQ walls) take two steps per launch
  * through the two-step kernel of lbm_set_variant(4). In the persistent form
  * (lbm_batch_set_persistent) the line instances of one equilibrium version take ONE launch for
- * all ceil(K/h) blocks: as many workgroups as are resident at once loop over the chunk list, and a
- * device-wide barrier with a bounded wait separates the blocks. One call of lbm_batch_step(b, K) is
+ * all ceil(K/h) blocks: as many workgroups as are resident at once take (block, chunk) tickets in
+ * order, and a chunk starts a block once the chunks whose nodes lie within h of its own have
+ * finished the block before (bounded waits on per-chunk epochs, no grid-wide barrier). One call
+ * of lbm_batch_step(b, K) is
  * captured once in a hipGraph and replayed on later calls with the same K.
  * Results equal those of lbm_step on each instance alone: with the fused kernel (variant 0)
  * bitwise for tiled instances (in two-step mode the plain ones with variant 4, bitwise), within
@@ -79,8 +81,8 @@ lbm_status lbm_batch_get_schedule(const lbm_batch* b, int32_t* region, int32_t* 
 
 /* Launch form of the line instances: persistent = 1, one launch per equilibrium version for the
  * whole of an lbm_batch_step call (grid = min(chunks, workgroups resident on the device), chunks
- * taken round-robin, a grid barrier between blocks of h steps); 0, one launch per block (the
- * form at creation). Results are bitwise the same. timeout_ms in [0, 60000] bounds each barrier
+ * taken in ticket order, each waiting for its neighbours' previous block); 0, one launch per
+ * block (the form at creation). Results are bitwise the same. timeout_ms in [0, 60000] bounds each
  * wait (wall clock; 0 gives up at once, for tests of the error path): a wait that runs out
  * raises a device error word, every workgroup leaves, and lbm_batch_check then returns
  * LBM_ETIMEOUT (the state is invalid; re-initialise). Overlapping calls on one batch race.
@@ -108,7 +110,7 @@ lbm_status lbm_batch_get_two_step(const lbm_batch* b, int32_t* on, int32_t* rows
 lbm_status lbm_batch_tune(lbm_batch* b, int64_t probe_steps, double* best_ms);
 
 /* As lbm_check, for the batch; LBM_ETIMEOUT (checked first, then cleared) if a persistent
- * launch's barrier wait timed out since the last check. */
+ * launch's wait timed out since the last check. */
 lbm_status lbm_batch_check(lbm_batch* b);
 
 void lbm_batch_destroy(lbm_batch* b);

@@ -159,7 +159,8 @@ class Batch:
     def set_persistent(self, persistent, timeout_ms=2000.0):
         """Line instances: one persistent launch per equilibrium version for a
         whole call (True) or one launch per block of h steps (False);
-        timeout_ms bounds each grid-barrier wait of the persistent launch."""
+        timeout_ms bounds each wait of the persistent launch for the chunks a
+        chunk depends on."""
         _check(_lib().lbm_batch_set_persistent(self.handle, int(persistent), float(timeout_ms)))
 
     def persistent(self):

@@ -18,10 +18,9 @@ namespace {
 constexpr int MIN_CHUNK = 32;
 
 // Device status words of a batch, each in a line of its own: health flag at
-// byte 0, barrier-timeout error at 64, the persistent launches' ticket
-// counter at 128, their barrier words (BAR_WORDS unsigned) from 256 (the
-// persistent kernel finds them from the flag's address).
-constexpr size_t STATUS_BYTES = 256 + 4 * BAR_WORDS;
+// byte 0, the persistent launches' time-out error at 64 and ticket counter
+// at 128 (the persistent kernel finds them from the flag's address).
+constexpr size_t STATUS_BYTES = 256;
 static_assert(STATUS_BYTES % 256 == 0, "the backup arena after the status words stays 256-byte aligned");
 
 struct Schedule {
@@ -42,7 +41,7 @@ void launch_line(const double* A, double* B, const LineInst* insts, const LineCh
 
 // Persistent line kernel of (version, region), as a function pointer.
 typedef void (*PersistentKernel)(double*, double*, const LineInst*, const LineChunk*, int, const int*, int, int, int*,
-                                 long long);
+                                 int*, long long);
 
 PersistentKernel persistent_kernel(int ver, int region) {
   if (region == 256)
@@ -52,8 +51,8 @@ PersistentKernel persistent_kernel(int ver, int region) {
                                                                : k_batch_line_persistent<1, 128>;
 }
 
-// Default bound on one grid-barrier wait of a persistent launch. A block of
-// h steps of a workgroup's share of the chunks takes well under a second.
+// Default bound on one wait of a persistent launch for the chunks another
+// depends on (each takes well under a millisecond).
 constexpr double DEFAULT_BARRIER_TIMEOUT_MS = 2000.0;
 
 }  // namespace
@@ -91,8 +90,9 @@ struct lbm_batch {
   int* budget;
   int* flag;       // health flag (flag[0]), first of the STATUS_BYTES status words
   unsigned long long* ctr;  // chunk ticket counter of the persistent launches
+  int* epoch;               // per chunk: the last block a persistent launch has finished
   int persistent;  // line instances: 1 one persistent launch per version, 0 one launch per h steps
-  long long timeout_ticks;  // bound on one barrier wait, wall-clock ticks
+  long long timeout_ticks;  // bound on one wait of a persistent launch, wall-clock ticks
   int resident[4][2];       // resident workgroups of the persistent kernel [version][region 128, 256]; 0 unknown
   int cur;   // current buffer of the line instances
   int cur2;  // current buffer of the tiled instances with walls or the flux-limited scheme
@@ -137,7 +137,8 @@ static int batch_tile_rows(const lbm_params* inst, int32_t n) {
 static int tile_variant(const lbm_params& p) { return p.scheme == 1 ? 2 : (has_walls(&p) ? 1 : 0); }
 
 struct Layout {
-  size_t arena_bytes, insts_off, chunks_off, tinsts_off, tiles_off, tiles2_off, budget_off, flag_off, backup_off, total;
+  size_t arena_bytes, insts_off, chunks_off, epoch_off, tinsts_off, tiles_off, tiles2_off, budget_off, flag_off,
+      backup_off, total;
   long long arena_doubles;
   int max_chunks, ntiled, ntiles, ntiles2;  // ntiles, ntiles2: at the smallest tile heights
   int rows;  // default rows per tile of the tiled instances
@@ -187,7 +188,8 @@ static lbm_status layout_of(const lbm_params* inst, int32_t n, Layout* L) {
   L->arena_bytes = align256((size_t)dbl * sizeof(double));
   L->insts_off = 2 * L->arena_bytes;
   L->chunks_off = L->insts_off + align256((size_t)n * sizeof(LineInst));
-  L->tinsts_off = L->chunks_off + align256((size_t)std::max<long long>(maxc, 1) * sizeof(LineChunk));
+  L->epoch_off = L->chunks_off + align256((size_t)std::max<long long>(maxc, 1) * sizeof(LineChunk));
+  L->tinsts_off = L->epoch_off + align256((size_t)std::max<long long>(maxc, 1) * sizeof(int));
   L->tiles_off = L->tinsts_off + align256((size_t)std::max(ntiled, 1) * sizeof(TileInst));
   L->tiles2_off = L->tiles_off + align256((size_t)(ntiles + 72 + 1) * sizeof(int2));
   L->budget_off = L->tiles2_off + align256((size_t)(ntiles2 + 24 + 1) * sizeof(int2));
@@ -213,8 +215,9 @@ static lbm_status build_chunks(lbm_batch* b, const Schedule& s) {
     for (int i = 0; i < b->n; ++i) {
       if (b->params[i].eq_version != ver || b->tiled[i]) continue;
       const int N = b->host_insts[i].N;
+      const int first = (int)ch.size();
       if (N <= s.region) {
-        ch.push_back(LineChunk{i, 0, N, 0});
+        ch.push_back(LineChunk{i, 0, N, 0, 0, {0, 0, 0}});
       } else {
         const int C = s.region - 2 * s.h;
         // A NEQ wall node takes its fluid neighbour's value of the same step,
@@ -224,9 +227,19 @@ static lbm_status build_chunks(lbm_batch* b, const Schedule& s) {
         while (st < N) {
           int len = std::min(C, N - st);
           if (b->host_insts[i].walls && N - st - len == 1) --len;
-          ch.push_back(LineChunk{i, st, len, 0});
+          ch.push_back(LineChunk{i, st, len, 0, 0, {0, 0, 0}});
           st += len;
         }
+      }
+      // chunks of this line whose nodes lie within h of chunk c's (list
+      // indices relative to the version's first chunk)
+      const int end = (int)ch.size();
+      for (int c = first; c < end; ++c) {
+        int lo = c, hi = c;
+        while (lo > first && ch[lo - 1].start + ch[lo - 1].len > ch[c].start - s.h) --lo;
+        while (hi + 1 < end && ch[hi + 1].start < ch[c].start + ch[c].len + s.h) ++hi;
+        ch[c].dlo = lo - b->vbegin[ver];
+        ch[c].dhi = hi - b->vbegin[ver];
       }
     }
     b->vend[ver] = (int)ch.size();
@@ -386,10 +399,12 @@ static hipError_t enqueue_steps(lbm_batch* b, int64_t nsteps, int start_cur, int
       int cap = 0;
       hipError_t e = resident_workgroups(b, ver, b->sched.region, &cap);
       if (e != hipSuccess) return e;
-      hipLaunchKernelGGL(k_persist_reset, dim3(1), dim3(1), 0, stream, b->ctr);
+      hipLaunchKernelGGL(k_persist_reset, dim3((nc + 255) / 256), dim3(256), 0, stream, b->ctr,
+                         b->epoch + b->vbegin[ver], nc);
       hipLaunchKernelGGL(persistent_kernel(ver, b->sched.region), dim3(std::min(nc, cap)), dim3(b->sched.region), 0,
-                         stream, b->arena[start_cur], b->arena[start_cur ^ 1], b->insts, b->chunks + b->vbegin[ver], nc,
-                         b->budget, (int)nsteps, b->sched.h, b->flag, b->timeout_ticks);
+                         stream, b->arena[start_cur], b->arena[start_cur ^ 1], b->insts, b->chunks + b->vbegin[ver],
+                         nc, b->budget, (int)nsteps, b->sched.h, b->epoch + b->vbegin[ver], b->flag,
+                         b->timeout_ticks);
       e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
@@ -514,6 +529,7 @@ lbm_status lbm_batch_create(const lbm_params* inst, int32_t n, void* d_workspace
   b->arena[1] = (double*)(base + L.arena_bytes);
   b->insts = (LineInst*)(base + L.insts_off);
   b->chunks = (LineChunk*)(base + L.chunks_off);
+  b->epoch = (int*)(base + L.epoch_off);
   b->tinsts = (TileInst*)(base + L.tinsts_off);
   b->tile_inst = (int2*)(base + L.tiles_off);
   b->tile_inst2 = (int2*)(base + L.tiles2_off);
@@ -843,15 +859,20 @@ lbm_status lbm_batch_tune(lbm_batch* b, int64_t probe_steps, double* best_ms) {
     if (build_chunks(b, tr.s) != LBM_OK) continue;
     b->persistent = tr.pers;
     // warm-up + timed trial, both without graphs
-    e = enqueue_steps(b, std::min<int64_t>(probe_steps, 2 * tr.s.h), b->cur, b->cur2, b->cur3, b->stream, 1);
+    // at least 8 blocks per trial, so that what happens between blocks
+    // (launch gaps, or the persistent form's waits) is weighed; the time is
+    // scaled back to probe_steps steps
+    const int64_t probe = std::max<int64_t>(probe_steps, 8 * (int64_t)tr.s.h);
+    e = enqueue_steps(b, std::min<int64_t>(probe, 2 * tr.s.h), b->cur, b->cur2, b->cur3, b->stream, 1);
     if (e == hipSuccess) e = hipEventRecord(t0, b->stream);
-    if (e == hipSuccess) e = enqueue_steps(b, probe_steps, b->cur, b->cur2, b->cur3, b->stream, 1);
+    if (e == hipSuccess) e = enqueue_steps(b, probe, b->cur, b->cur2, b->cur3, b->stream, 1);
     if (e == hipSuccess) e = hipEventRecord(t1, b->stream);
     if (e == hipSuccess) e = hipEventSynchronize(t1);
     if (e != hipSuccess) break;
     float ms = 0;
     e = hipEventElapsedTime(&ms, t0, t1);
     if (e != hipSuccess) break;
+    ms *= (float)probe_steps / (float)probe;
     if (ms < best_t) {
       best_t = ms;
       best = tr.s;
@@ -865,12 +886,12 @@ lbm_status lbm_batch_tune(lbm_batch* b, int64_t probe_steps, double* best_ms) {
   (void)hipEventDestroy(t1);
   if (!any_line) best_t = 0.0f;
   if (e == hipSuccess) e = hipMemcpyAsync(b->arena[saved_cur], b->backup, bytes, hipMemcpyDeviceToDevice, b->stream);
-  int word[17] = {0};  // a timed-out barrier in a trial voids the persistent form
+  int word[17] = {0};  // a timed-out wait in a trial voids the persistent form
   if (e == hipSuccess) e = hipMemcpyAsync(word, b->flag, sizeof(word), hipMemcpyDeviceToHost, b->stream);
   if (e == hipSuccess) e = hipMemsetAsync(b->flag, 0, STATUS_BYTES, b->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) return hip_fail(e, "tuning run");
-  if (word[16]) return fail(LBM_ETIMEOUT, "a grid barrier of a persistent trial timed out");
+  if (word[16]) return fail(LBM_ETIMEOUT, "a wait of a persistent trial timed out");
   b->cur = saved_cur;
   b->persistent = best_pers;
   lbm_status st = build_chunks(b, best);
@@ -999,11 +1020,11 @@ lbm_status lbm_batch_check(lbm_batch* b) {
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) return hip_fail(e, "reading the health flag");
   const int flag = word[0];
-  if (word[16]) {  // a barrier wait timed out: clear err, the barrier and the flag
+  if (word[16]) {  // a wait timed out: clear the error word, the counters and the flag
     e = hipMemsetAsync(b->flag, 0, STATUS_BYTES, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
-    return fail(LBM_ETIMEOUT, "a grid barrier of the persistent launch timed out; the state is invalid");
+    return fail(LBM_ETIMEOUT, "a wait of the persistent launch timed out; the state is invalid");
   }
   if (flag) {
     e = hipMemsetAsync(b->flag, 0, sizeof(int), b->stream);

@@ -27,7 +27,8 @@ struct LineChunk {
   int inst;
   int start;
   int len;
-  int pad;
+  int dlo, dhi;  // chunks (list indices) whose output of a block this chunk's next block reads or overwrites
+  int pad[3];
 };
 
 // Ghost of line end `end` (0 low, 1 high) from the end node's distributions.
@@ -186,83 +187,6 @@ __global__ __launch_bounds__(REGION, 2) void k_batch_line(const double* __restri
   if (!line_chunk<VER, REGION>(A, B, insts, chunks, blockIdx.x, budget, n0, h)) flag[0] = 1;
 }
 
-// Grid-wide barrier of a persistent launch (every workgroup resident at
-// once), arranged as a two-level tree so that no counter takes more than
-// ~32 arrivals (arrivals on one device-scope counter are serialised, and a
-// flat counter over 512-1024 workgroups costs tens of microseconds).
-// Workgroup b belongs to group b mod G, G = min(BAR_GROUPS, grid). Words,
-// each group's in lines of their own (unsigned, stride BAR_STRIDE):
-//   bar[0]                              groups arrived (top counter)
-//   bar[BAR_STRIDE (1 + g)]             arrivals of group g
-//   bar[BAR_STRIDE (1 + g) + STRIDE/2]  generation seen by group g
-// The last arrival of a group arrives at the top counter; the last group
-// to arrive there advances every group's generation, which the group's
-// members poll. Stores before the barrier are released and loads after it
-// acquired at device (agent) scope, which spans the L2 caches of all XCDs;
-// every counter is back at 0 after a barrier that completes. The wait is
-// bounded: a workgroup that has waited `timeout` ticks of the constant-rate
-// wall clock (timeout 0: any workgroup that would wait) raises err[0] and
-// gives up, and every workgroup that sees err[0] raised leaves too, so the
-// launch always ends; the host reports the error and the state is invalid.
-constexpr int BAR_GROUPS = 32;
-constexpr int BAR_STRIDE = 64;  // unsigned words: 256 bytes
-constexpr int BAR_WORDS = BAR_STRIDE * (1 + BAR_GROUPS);
-
-__device__ __forceinline__ bool grid_barrier(unsigned* bar, int* err, long long timeout) {
-  __shared__ int ok_s;
-  __syncthreads();  // the whole workgroup's stores are issued and complete
-  if (threadIdx.x == 0) {
-    int ok = 1;
-    const unsigned G = min((unsigned)BAR_GROUPS, gridDim.x);
-    const unsigned g = blockIdx.x % G;
-    const unsigned members = (gridDim.x - g + G - 1) / G;
-    unsigned* cnt = bar + BAR_STRIDE * (1 + g);
-    unsigned* gen_p = cnt + BAR_STRIDE / 2;
-    // Only fences order memory; the counters themselves are relaxed (a
-    // fence plus a relaxed atomic synchronises like a release or acquire
-    // atomic, and each fence costs an L2 write-back or invalidate).
-    // (the generation is read before the release, which keeps the read
-    // ahead of this workgroup's arrival)
-    const unsigned gen = __hip_atomic_load(gen_p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    bool wait = true;
-    if (__hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == members - 1) {
-      __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");  // the group's arrivals, passed on
-      if (__hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == G - 1) {
-        __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");  // every group's arrivals, passed on
-        for (unsigned k = 0; k < G; ++k)
-          __hip_atomic_store(bar + BAR_STRIDE * (1 + k) + BAR_STRIDE / 2, gen + 1u, __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-        wait = false;
-      }
-    }
-    if (wait) {
-      if (timeout <= 0) {  // no wait allowed: give up
-        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        ok = 0;
-      } else {
-        const long long t0 = wall_clock64();
-        for (unsigned n = 1; __hip_atomic_load(gen_p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen; ++n) {
-          if ((n & 7) == 0 &&
-              (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) || wall_clock64() - t0 >= timeout)) {
-            __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            ok = 0;
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-        }
-      }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
-    ok_s = ok;
-  }
-  __syncthreads();
-  return ok_s != 0;
-}
-
 // A value every lane holds alike (read from LDS), marked workgroup-uniform
 // so that what derives from it (the chunk and its instance) stays in scalar
 // registers and uniform branches.
@@ -272,52 +196,91 @@ __device__ __forceinline__ unsigned long long uniform_u64(unsigned long long v) 
   return ((unsigned long long)hi << 32) | lo;
 }
 
+// Start of a persistent launch: ticket counter 0, every chunk's epoch -1 (a
+// kernel, so that it can sit in a captured graph).
+__global__ void k_persist_reset(unsigned long long* ctr, int* epoch, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *ctr = 0ull;
+  if (i < n) epoch[i] = -1;
+}
+
 // Persistent form of the line kernel: one launch advances every chunk of
-// one equilibrium version through all the ceil(nsteps / h) blocks of h
-// steps of a call. The grid holds at most as many workgroups as are
-// resident on the device at once, and a grid barrier separates the blocks
-// (a chunk's halo comes from its neighbours' output of the block before).
-// Chunks are handed out in ticket order from one counter (ctr, zero at
-// launch): ticket k is chunk k mod nchunks of block k / nchunks, so the
-// workgroups balance the load as the hardware dispatcher would. A
-// workgroup fetches its next ticket while it works on a chunk; a ticket of
-// the next block is kept until the barrier is passed (there are at most
-// grid <= nchunks such tickets, so they all fall in the next block).
-// src: the buffer holding the state at the start, dst the other one.
-// status: the batch's status words (health flag at word 0, error word at
-// 16, ticket counter at 32, barrier words from 64).
+// one equilibrium version through all the ceil(nsteps / h) blocks of h steps
+// of a call. The grid holds at most as many workgroups as are resident at
+// once. Chunks are handed out in ticket order from one counter (ticket k:
+// chunk k mod nchunks of block k / nchunks), so the workgroups balance the
+// load as the hardware dispatcher would; a workgroup fetches its next ticket
+// while it works on a chunk. There is no grid-wide barrier between blocks:
+// a workgroup starts chunk c of block k once the chunks dlo(c) .. dhi(c)
+// have finished block k - 1 (their epoch >= k - 1): those wrote the region c
+// reads in block k and read, as halo, the region c overwrites. Each finished
+// chunk publishes its epoch after a release fence at device (agent) scope,
+// which spans the L2 caches of all XCDs; the wait ends with an acquire fence.
+// Tickets are handed out in order, so every chunk waited for is held by a
+// running workgroup that waits only on earlier blocks, and the waits end.
+// Each wait is bounded all the same: after `timeout` ticks of the
+// constant-rate wall clock (timeout 0: at once) the workgroup raises the
+// error word and leaves, and so does every workgroup that sees it raised;
+// the host reports the error and the state is then invalid.
+// status: health flag at word 0, error word at 16, ticket counter at 32.
 template <int VER, int REGION>
 __global__ __launch_bounds__(REGION, 2) void k_batch_line_persistent(double* src, double* dst,
-                                                                     const LineInst* __restrict__ insts,
-                                                                     const LineChunk* __restrict__ chunks, int nchunks,
-                                                                     const int* __restrict__ budget, int nsteps, int h,
-                                                                     int* status, long long timeout) {
+                                                               const LineInst* __restrict__ insts,
+                                                               const LineChunk* __restrict__ chunks, int nchunks,
+                                                               const int* __restrict__ budget, int nsteps, int h,
+                                                               int* epoch, int* status, long long timeout) {
   unsigned long long* ctr = reinterpret_cast<unsigned long long*>(status + 32);
-  bool ok = true;
+  int* err = status + 16;
   __shared__ unsigned long long tk_s[2];
+  __shared__ int go_s;
+  const unsigned long long nblocks = (unsigned long long)((nsteps + h - 1) / h);
+  const unsigned long long last = nblocks * (unsigned long long)nchunks;
+  bool ok = true;
   if (threadIdx.x == 0) tk_s[0] = __hip_atomic_fetch_add(ctr, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
   unsigned long long tk = uniform_u64(tk_s[0]);
   int par = 1;
-  for (int n0 = 0, blk = 0; n0 < nsteps; n0 += h, ++blk) {
+  while (tk < last) {
+    const int blk = (int)(tk / (unsigned long long)nchunks);
+    const int ci = (int)(tk - (unsigned long long)blk * (unsigned long long)nchunks);
+    if (threadIdx.x == 0) {
+      int go = 1;
+      if (blk > 0) {
+        const LineChunk& ch = chunks[ci];
+        const long long t0 = wall_clock64();
+        for (int d = ch.dlo; d <= ch.dhi && go; ++d) {
+          for (unsigned n = 1; __hip_atomic_load(&epoch[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < blk - 1;
+               ++n) {
+            if (timeout <= 0 || ((n & 7) == 0 && (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+                                                  wall_clock64() - t0 >= timeout))) {
+              __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              go = 0;
+              break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      }
+      go_s = go;
+    }
+    __syncthreads();
+    if (!go_s) break;
+    const int n0 = blk * h;
     const int hb = min(h, nsteps - n0);
     const double* A = (blk & 1) ? dst : src;
     double* B = (blk & 1) ? src : dst;
-    const unsigned long long first = (unsigned long long)blk * (unsigned long long)nchunks, end = first + nchunks;
-    while (tk < end) {
-      ok &= line_chunk<VER, REGION, true>(A, B, insts, chunks, (int)(tk - first), budget, n0, hb, ctr, &tk_s[par]);
-      __syncthreads();  // also: this chunk is done with the LDS buffers
-      tk = uniform_u64(tk_s[par]);
-      par ^= 1;
+    ok &= line_chunk<VER, REGION, true>(A, B, insts, chunks, ci, budget, n0, hb, ctr, &tk_s[par]);
+    __syncthreads();  // the chunk's stores are issued and complete; LDS free for the next one
+    if (threadIdx.x == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_store(&epoch[ci], blk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    if (n0 + h < nsteps && !grid_barrier(reinterpret_cast<unsigned*>(status + 64), status + 16, timeout)) break;
+    tk = uniform_u64(tk_s[par]);
+    par ^= 1;
   }
   if (!ok) status[0] = 1;
 }
-
-// Zeroes the ticket counter of a persistent launch (a kernel, so that it can
-// sit in a captured graph).
-__global__ void k_persist_reset(unsigned long long* ctr) { *ctr = 0ull; }
 
 }  // namespace lbm
 

@@ -1,9 +1,10 @@
 """Persistent form of the batched line kernel: one launch per equilibrium
-version runs every block of h steps of a call, with a device-wide barrier
-between blocks. It must give bitwise the result of one launch per block, in
-and out of a hipGraph, with budgets, mixed versions and tiled instances, and
-its bounded barrier wait must end every launch and be reported when it runs
-out (forced from the host with a zero time limit)."""
+version runs every block of h steps of a call, each chunk starting a block
+once the chunks it depends on have finished the block before. It must give
+bitwise the result of one launch per block, in and out of a hipGraph, with
+budgets, mixed versions and tiled instances, at schedules whose halo spans
+several chunks, and its bounded waits must end every launch and be reported
+when they run out (forced from the host with a zero time limit)."""
 
 import numpy as np
 import pytest
@@ -42,7 +43,7 @@ def _run(items, steps, region, h, persistent, use_graph=True, budgets=None, call
 
 
 @pytest.mark.parametrize("region,h,steps", [(128, 8, 100), (256, 16, 100), (256, 32, 37), (128, 1, 5),
-                                            (256, 24, 24), (128, 4, 3)])
+                                            (256, 24, 24), (128, 4, 3), (256, 112, 230), (128, 48, 100)])
 def test_persistent_equals_block_launches(region, h, steps):
     items = _lines(21, 40, riemann_n=(256, 2500), couette_h=(32, 256))
     ref, _ = _run(items, steps, region, h, False, use_graph=False)
@@ -115,8 +116,8 @@ def test_persistent_graph_replays_match_eager_runs():
     e.close()
 
 
-def test_barrier_timeout_is_reported_and_cleared():
-    """A zero time limit makes every workgroup that would wait at a barrier
+def test_wait_timeout_is_reported_and_cleared():
+    """A zero time limit makes every workgroup that would wait for a chunk
     give up: the launch ends, the batch reports LBM_ETIMEOUT once, and after
     re-initialisation the persistent form is exact again."""
     from paper_1106_0785_amd import lbm
@@ -126,7 +127,7 @@ def test_barrier_timeout_is_reported_and_cleared():
     b.set_schedule(256, 16)
     b.set_persistent(True, timeout_ms=0.0)
     assert b.persistent()["grid"] >= 2
-    b.step(64)  # 4 blocks, 3 barriers
+    b.step(64)  # 4 blocks
     with pytest.raises(lbm.LbmError) as err:
         b.check()
     assert err.value.status == -6
