@@ -83,7 +83,8 @@ lbm_status lbm_batch_get_schedule(const lbm_batch* b, int32_t* region, int32_t* 
  * whole of an lbm_batch_step call (grid = min(chunks, workgroups resident on the device), chunks
  * taken in ticket order, each waiting for its neighbours' previous block); 0, one launch per
  * block (the form at creation). Results are bitwise the same. timeout_ms in [0, 60000] bounds each
- * wait (wall clock; 0 gives up at once, for tests of the error path): a wait that runs out
+ * wait (wall clock; 0: the first dependency check of a call with two or more blocks raises the
+ * error, for tests of the error path): a wait that runs out
  * raises a device error word, every workgroup leaves, and lbm_batch_check then returns
  * LBM_ETIMEOUT (the state is invalid; re-initialise). Overlapping calls on one batch race.
  * grid (get): workgroups of the largest persistent launch of the current schedule. */

@@ -219,8 +219,9 @@ __global__ void k_persist_reset(unsigned long long* ctr, int* epoch, int n) {
 // Tickets are handed out in order, so every chunk waited for is held by a
 // running workgroup that waits only on earlier blocks, and the waits end.
 // Each wait is bounded all the same: after `timeout` ticks of the
-// constant-rate wall clock (timeout 0: at once) the workgroup raises the
-// error word and leaves, and so does every workgroup that sees it raised;
+// constant-rate wall clock the workgroup raises the error word and leaves,
+// and so does every workgroup that sees it raised (timeout 0: the first
+// check of a chunk's dependencies raises it, met or not, for tests);
 // the host reports the error and the state is then invalid.
 // status: health flag at word 0, error word at 16, ticket counter at 32.
 template <int VER, int REGION>
@@ -245,14 +246,17 @@ __global__ __launch_bounds__(REGION, 2) void k_batch_line_persistent(double* src
     const int ci = (int)(tk - (unsigned long long)blk * (unsigned long long)nchunks);
     if (threadIdx.x == 0) {
       int go = 1;
-      if (blk > 0) {
+      if (blk > 0 && timeout <= 0) {  // no waiting allowed: the first check gives up
+        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        go = 0;
+      } else if (blk > 0) {
         const LineChunk& ch = chunks[ci];
         const long long t0 = wall_clock64();
         for (int d = ch.dlo; d <= ch.dhi && go; ++d) {
           for (unsigned n = 1; __hip_atomic_load(&epoch[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < blk - 1;
                ++n) {
-            if (timeout <= 0 || ((n & 7) == 0 && (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
-                                                  wall_clock64() - t0 >= timeout))) {
+            if ((n & 7) == 0 && (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+                                 wall_clock64() - t0 >= timeout)) {
               __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
               go = 0;
               break;

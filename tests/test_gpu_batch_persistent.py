@@ -117,9 +117,10 @@ def test_persistent_graph_replays_match_eager_runs():
 
 
 def test_wait_timeout_is_reported_and_cleared():
-    """A zero time limit makes every workgroup that would wait for a chunk
-    give up: the launch ends, the batch reports LBM_ETIMEOUT once, and after
-    re-initialisation the persistent form is exact again."""
+    """A zero time limit makes the first check of a chunk's dependencies
+    (block 1 on) give up: every workgroup leaves, the launch ends, the batch
+    reports LBM_ETIMEOUT once, and after re-initialisation the persistent
+    form is exact again."""
     from paper_1106_0785_amd import lbm
 
     items = _lines(27, 24, riemann_n=(600, 2000), couette_h=(32, 200))
