@@ -156,8 +156,6 @@ static lbm_status layout_of(const lbm_params* inst, int32_t n, Layout* L) {
   }
   L->rows = batch_tile_rows(inst, n);
   for (int i = 0; i < n; ++i) {
-    lbm_status st = LBM_OK;
-    if (st != LBM_OK) return fail(st, "instance %d: %s", i, lbm_last_error());
     const lbm_params& p = inst[i];
     if (is_line(p)) {
       const long long N = line_len(p);
@@ -713,6 +711,11 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps) {
     if (b->graph_steps[c] != nsteps) {
       if (b->graph[c]) (void)hipGraphExecDestroy(b->graph[c]);
       b->graph[c] = nullptr;
+      if (b->persistent) {  // occupancy queries outside the capture
+        int32_t grid = 0;
+        lbm_status st = lbm_batch_get_persistent(b, nullptr, &grid);
+        if (st != LBM_OK) return st;
+      }
       hipGraph_t g = nullptr;
       hipError_t e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal);
       if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");

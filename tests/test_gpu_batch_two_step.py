@@ -1,6 +1,6 @@
 """Two-step mode of the batched form: the plain tiled instances (Lax-Wendroff,
-no NEQ walls) advance two steps per launch through the two-step kernel, one
-step when only one is left in the call or in their budget. Each such
+no NEQ walls) advance two steps per launch through the two-step kernel
+(mode 1), one step when only one is left in the call or in their budget. Each such
 instance must end bitwise where lbm_step with the two-step kernel (variant
 4) puts it alone, the other instances where they always did, every instance
 within 1e-11 of the oracle; graph replays, budgets, mode changes between
@@ -13,6 +13,14 @@ from gpu_util import assert_parity, gpu_run, log, oracle_run
 from paper_1106_0785_amd import inputs
 
 pytestmark = pytest.mark.gpu
+
+# A persistent form of the two-step tiles (every pair of a call in one launch,
+# mode 2) was tried and taken out: its first GPU run went silent in the first
+# mode-2 case, and reading the code found no cause. set_two_step rejects 2;
+# the mode-2 cases stay here, skipped, as the record of it.
+_MODE2_GONE = pytest.mark.skip(reason="persistent two-step form (mode 2) taken out: its first GPU run "
+                                      "hung with no cause found by reading the code")
+MODES = [1, pytest.param(2, marks=_MODE2_GONE)]
 
 
 def _mixed(seed, n):
@@ -55,10 +63,11 @@ def _check_against_single(items, b, fb, steps_of):
     return plain
 
 
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("steps", [150, 151])
-def test_two_step_mode_matches_single_problem_paths_and_oracle(steps):
+def test_two_step_mode_matches_single_problem_paths_and_oracle(steps, mode):
     items, b = _mixed(3, 18)
-    b.set_two_step(True, 16)
+    b.set_two_step(mode, 16)
     b.step(steps)
     b.check()
     fb = b.get_f().cpu().numpy()
@@ -68,12 +77,14 @@ def test_two_step_mode_matches_single_problem_paths_and_oracle(steps):
     b.close()
 
 
-def test_two_step_mode_with_budgets():
-    """Budgets of both parities, below and above the call's length."""
+@pytest.mark.parametrize("mode", MODES)
+def test_two_step_mode_with_budgets(mode):
+    """Budgets of both parities, below and above the call's length, and 0."""
     items, b = _mixed(8, 18)
     budgets = [11 * (i + 1) + (i % 3) for i in range(len(items))]
+    budgets[5] = 0
     b.set_budgets(budgets)
-    b.set_two_step(True, 8)
+    b.set_two_step(mode, 8)
     b.step(101)
     b.check()
     fb = b.get_f().cpu().numpy()
@@ -81,17 +92,18 @@ def test_two_step_mode_with_budgets():
     b.close()
 
 
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("rows", [2, 8, 32, 128])
-def test_two_step_tile_heights_agree(rows):
+def test_two_step_tile_heights_agree(rows, mode):
     items, b = _mixed(13, 12)
     items, r = _mixed(13, 12)
     budgets = [7 * (i + 2) + (i % 2) for i in range(len(items))]
     b.set_budgets(budgets)
     r.set_budgets(budgets)
-    b.set_two_step(True, rows)
-    r.set_two_step(True, 16)
+    b.set_two_step(mode, rows)
+    r.set_two_step(1, 16)
     info = b.two_step()
-    assert info["two_step"] and info["tile_rows2"] == rows and info["tiles2"] > 0
+    assert info["two_step"] == mode and info["tile_rows2"] == rows and info["tiles2"] > 0
     b.step(61)
     r.step(61)
     assert np.array_equal(b.get_f().cpu().numpy(), r.get_f().cpu().numpy())
@@ -99,15 +111,16 @@ def test_two_step_tile_heights_agree(rows):
     r.close()
 
 
-def test_two_step_graph_replays_match_eager_runs():
+@pytest.mark.parametrize("mode", MODES)
+def test_two_step_graph_replays_match_eager_runs(mode):
     import torch
 
     items, g = _mixed(9, 12)
     items, e = _mixed(9, 12)
     g.set_schedule(256, 16, use_graph=True)
     e.set_schedule(256, 16, use_graph=False)
-    g.set_two_step(True, 16)
-    e.set_two_step(True, 16)
+    g.set_two_step(mode, 16)
+    e.set_two_step(1, 16)
     for rep, k in enumerate((47, 47, 30, 47, 1)):
         g.step(k)
         e.step(k)
@@ -121,16 +134,16 @@ def test_two_step_graph_replays_match_eager_runs():
 
 
 def test_mode_changes_between_calls():
-    """One-step, two-step and one-step calls in turn (odd lengths, so the
-    kinds of instance sit in different buffers at each change): the result
-    is that of the same calls made by lbm_step on each instance (variant 0,
-    4, 0), and within 1e-11 of the oracle."""
+    """One-step and two-step calls in turn (odd lengths, so the kinds of
+    instance sit in different buffers at each change): the result is that of
+    the same calls made by lbm_step on each instance (variant 0, 4, ...),
+    and within 1e-11 of the oracle."""
     from paper_1106_0785_amd import lbm
 
     items, b = _mixed(5, 12)
-    plan = ((0, 33), (1, 41), (0, 17))
+    plan = ((0, 33), (1, 41), (0, 17), (1, 29), (1, 6), (0, 1), (1, 1))
     for mode, k in plan:
-        b.set_two_step(bool(mode), 16)
+        b.set_two_step(mode, 16)
         b.step(k)
     b.check()
     fb = b.get_f().cpu().numpy()
@@ -166,7 +179,7 @@ def test_set_two_step_rejects_bad_arguments():
     from paper_1106_0785_amd import lbm
 
     items, b = _mixed(1, 6)
-    for args in ((2, 16), (1, 3), (1, 0), (1, 8192)):
+    for args in ((2, 16), (3, 16), (-1, 16), (1, 3), (1, 0), (1, 8192)):
         with pytest.raises(lbm.LbmError):
             b.set_two_step(*args)
     b.close()
