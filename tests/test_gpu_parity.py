@@ -506,9 +506,9 @@ def test_window_shapes_are_checked():
 
 @pytest.mark.parametrize("case", ["sod_2000x4", "rm_256x64", "rm_300x100"])
 def test_tuner_picks_a_kernel_and_keeps_the_state(case):
-    """The tuner times fused tile shapes and window shapes, keeps the
-    fastest kernel, and restores the state; the run that follows matches
-    the oracle."""
+    """The tuner times fused tile shapes, window shapes and two-step tile
+    shapes, keeps the fastest kernel (variant 0, 3 or 4), and restores the
+    state; the run that follows matches the oracle."""
     from paper_1106_0785_amd import lbm
 
     if case == "sod_2000x4":
@@ -522,7 +522,7 @@ def test_tuner_picks_a_kernel_and_keeps_the_state(case):
     sim.tune(probe_steps=8)
     variant = sim.variant()
     log("tuner on %s: variant %d, window %s, tile %s" % (case, variant, sim.window(), sim.tile()))
-    assert variant in (0, 3)
+    assert variant in (0, 3, 4)
     assert np.array_equal(sim.get_f().cpu().numpy(), f0)
     sim.step(100)
     g = {k: v.cpu().numpy() for k, v in sim.moments().items()}
