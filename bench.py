@@ -122,7 +122,8 @@ def bench_batch(steps, seed=0, n=512, plain=True, two_d=False):
     b.check()
     # both launch forms of the line instances at the tuned schedule, each
     # captured in a graph: one launch per block of h steps, and one
-    # persistent launch per equilibrium version with grid barriers between blocks
+    # persistent launch per equilibrium version (each chunk waits for its
+    # neighbours' previous block)
     forms = {}
     for name, pers in (("per_block", False), ("persistent", True)) if sched["chunks"] else ():
         b.set_persistent(pers)
