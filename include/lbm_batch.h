@@ -107,7 +107,8 @@ lbm_status lbm_batch_get_two_step(const lbm_batch* b, int32_t* on, int32_t* rows
  * steps of the line instances, then tile heights 8 ... 128 (one step per launch) and, with
  * plain tiled instances, two-step tile heights 8 ... 128 for probe_steps steps of the tiled
  * instances, on the current state (synchronising the stream); restores the state and keeps
- * the fastest of each; *best_ms receives the sum of the two best times. */
+ * the fastest of each; *best_ms receives the sum of the two best times. An error left by earlier
+ * calls (what lbm_batch_check would return) is returned first, and nothing is tuned. */
 lbm_status lbm_batch_tune(lbm_batch* b, int64_t probe_steps, double* best_ms);
 
 /* As lbm_check, for the batch; LBM_ETIMEOUT (checked first, then cleared) if a persistent

@@ -828,6 +828,10 @@ lbm_status lbm_batch_get_persistent(lbm_batch* b, int32_t* persistent, int32_t* 
 lbm_status lbm_batch_tune(lbm_batch* b, int64_t probe_steps, double* best_ms) {
   if (!b) return fail(LBM_EINVAL, "batch is NULL");
   if (probe_steps < 1) return fail(LBM_EINVAL, "probe_steps must be >= 1");
+  // an error left by earlier calls is reported (and cleared) as lbm_batch_check
+  // does, before the trials, whose own status words are then discarded
+  lbm_status pending = lbm_batch_check(b);
+  if (pending != LBM_OK) return pending;
   // keep the current state: every trial runs from a backup copy
   const size_t bytes = (size_t)b->arena_doubles * sizeof(double);
   // (the schedule concerns the line instances only; the trials leave the

@@ -112,6 +112,22 @@ def test_tuner_keeps_state_and_picks_a_schedule():
     b.close()
 
 
+def test_tuner_reports_an_earlier_health_error_first():
+    """A step that went non-finite before the tuner is called: the tuner
+    returns LBM_ENONFINITE (as lbm_batch_check would) instead of tuning and
+    clearing the flag with its own trials."""
+    from paper_1106_0785_amd import lbm
+
+    items, b = _batch(12, 8)
+    items[3][2]["T"][:] = -1.0
+    b.init([f for _, _, f in items])
+    b.step(8)
+    with pytest.raises(lbm.LbmError) as err:
+        b.tune(probe_steps=8, use_cache=False)
+    assert err.value.status == -5
+    b.close()
+
+
 # ---------------------------------------------------------------------------
 # Batches mixing one-dimensional lines with two-dimensional (tiled) instances.
 # ---------------------------------------------------------------------------
