@@ -165,3 +165,35 @@ def test_set_persistent_rejects_bad_arguments():
         with pytest.raises(lbm.LbmError):
             b.set_persistent(*args)
     b.close()
+
+
+def test_persistent_with_every_budget_zero():
+    """Budgets of 0 for every instance: each chunk only carries its nodes over
+    block after block, in ticket order, and the state comes out unchanged."""
+    items = _lines(33, 12, riemann_n=(256, 1500), couette_h=(32, 120))
+    b = _make(items)
+    f0 = b.get_f().cpu().numpy()
+    b.close()
+    for steps in (50, 51):
+        f, info = _run(items, steps, 256, 16, True, budgets=[0] * len(items))
+        assert info["grid"] > 0
+        assert np.array_equal(f, f0)
+
+
+def test_persistent_form_without_line_instances():
+    """A batch of two-dimensional instances only: there is no line chunk to
+    launch persistently (grid 0) and the tiled instances advance as before."""
+    from paper_1106_0785_amd.batch import Batch
+
+    items = inputs.rm_batch(seed=2, n=4)
+    out = []
+    for pers in (False, True):
+        b = Batch([p for _, p, _ in items])
+        b.init([f for _, _, f in items])
+        b.set_persistent(pers)
+        assert b.persistent()["grid"] == 0
+        b.step(9)
+        b.check()
+        out.append(b.get_f().cpu().numpy())
+        b.close()
+    assert np.array_equal(out[0], out[1])
