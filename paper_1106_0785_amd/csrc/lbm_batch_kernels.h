@@ -82,17 +82,20 @@ __device__ __forceinline__ bool line_chunk(const double* __restrict__ A, double*
   const int hi = periodic ? N : min(ch.start + ch.len + steps, N);
   const int R = hi - lo;  // <= REGION (guaranteed by the chunking)
 
-  // load the region and its velocities
+  // load the region and its velocities; each thread keeps its node's moments
+  // (and 1 / rho) from one step to the next, for the collision and for the
+  // velocity its neighbours read
+  double m[16], ir = 0.0;
   if (t < R) {
     double f[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) f[i] = A[off + (long long)i * stride + lo + t];
-    double ux, uy;
-    velocity_of(f, ux, uy);
+    moments_from_f(f, m);
+    ir = 1.0 / m[0];
 #pragma unroll
     for (int i = 0; i < 16; ++i) buf[0][i][t] = f[i];
-    buf[0][16][t] = ux;
-    buf[0][17][t] = uy;
+    buf[0][16][t] = m[1] * ir;
+    buf[0][17][t] = m[2] * ir;
   }
   __syncthreads();
   unsigned long long next = 0;
@@ -134,21 +137,24 @@ __device__ __forceinline__ bool line_chunk(const double* __restrict__ A, double*
         velocity_of(fp, uxp, uyp);
       }
       const double ux0 = buf[P][16][t], uy0 = buf[P][17][t];
-      NbrVel nv;
-      double out[16];
+      // the step's arithmetic along the line's axis (the other axis's zero
+      // convection terms left out), the collision from the kept moments
+      double df[16], out[16];
       if (I.axis == 0) {
-        nv = NbrVel{uxp, uyp, uxm, uym, ux0, uy0, ux0, uy0};
-        ok &= node_update_line<VER, 0>(c, f, fp, fm, nv, out);
+        ok &= collide_from_moments<VER>(c, m, ir, NbrVel{uxp, uyp, uxm, uym, ux0, uy0, ux0, uy0}, df);
+        ConvAxis<0, 0>::run(c, f, fp, fm, out);
       } else {
-        nv = NbrVel{ux0, uy0, ux0, uy0, uxp, uyp, uxm, uym};
-        ok &= node_update_line<VER, 1>(c, f, fp, fm, nv, out);
+        ok &= collide_from_moments<VER>(c, m, ir, NbrVel{ux0, uy0, ux0, uy0, uxp, uyp, uxm, uym}, df);
+        ConvAxis<0, 1>::run(c, f, fp, fm, out);
       }
-      double ux, uy;
-      velocity_of(out, ux, uy);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) out[i] = f[i] + (out[i] + df[i]);
+      moments_from_f(out, m);
+      ir = 1.0 / m[0];
 #pragma unroll
       for (int i = 0; i < 16; ++i) buf[Q][i][t] = out[i];
-      buf[Q][16][t] = ux;
-      buf[Q][17][t] = uy;
+      buf[Q][16][t] = m[1] * ir;
+      buf[Q][17][t] = m[2] * ir;
     }
     __syncthreads();
     if (I.walls) {  // wall nodes from their neighbour's new distributions
@@ -158,12 +164,14 @@ __device__ __forceinline__ bool line_chunk(const double* __restrict__ A, double*
 #pragma unroll
         for (int i = 0; i < 16; ++i) fn[i] = buf[Q][i][r];
         neq_wall<VER>(I.cold.wall[2 * I.axis + (g == 0 ? 0 : 1)], fn, fw);
-        double ux, uy;
-        velocity_of(fw, ux, uy);
+        // its velocity as any node's (from its moments), so that it does not
+        // depend on whether the next step reloads the node
+        moments_from_f(fw, m);
+        ir = 1.0 / m[0];
 #pragma unroll
         for (int i = 0; i < 16; ++i) buf[Q][i][t] = fw[i];
-        buf[Q][16][t] = ux;
-        buf[Q][17][t] = uy;
+        buf[Q][16][t] = m[1] * ir;
+        buf[Q][17][t] = m[2] * ir;
       }
       __syncthreads();
     }

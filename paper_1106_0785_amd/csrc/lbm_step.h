@@ -153,19 +153,17 @@ struct ConvAxis<16, AXIS> {
   LBM_HD static void run(const Hot&, const double*, const double*, const double*, double*) {}
 };
 
-// Collision of one node in velocity space, -dt M^-1 Q (Sec. II), into df.
-// Returns false when rho <= 0, T <= 0 or a NaN appears.
+// Collision of one node in velocity space, -dt M^-1 Q (Sec. II), into df,
+// from the node's moments m = M f and ir = 1 / m[0]. Returns false when
+// rho <= 0, T <= 0 or a NaN appears.
 template <int VER>
-LBM_HD bool collide_delta(const Hot& c, const double* f, const NbrVel& nv, double* df) {
-  double m[16];
-  moments_from_f(f, m);
+LBM_HD bool collide_from_moments(const Hot& c, const double* m, double ir, const NbrVel& nv, double* df) {
   const double rho = m[0], jx = m[1], jy = m[2], e = m[3];
   double q[16];
   equilibrium_moments<VER, double>(rho, jx, jy, e, q);
   double col[16];
 #pragma unroll
   for (int k = 4; k < 16; ++k) col[k] = c.cq[k - 4] * (m[k] - q[k]);
-  const double ir = 1.0 / rho;
   const double ux = jx * ir, uy = jy * ir;
   const double T = e * ir - 0.5 * (ux * ux + uy * uy);
   {
@@ -179,6 +177,14 @@ LBM_HD bool collide_delta(const Hot& c, const double* f, const NbrVel& nv, doubl
   }
   f_from_nonconserved(col, df);
   return (rho > 0.0) && (T > 0.0);
+}
+
+// The same from the distributions f.
+template <int VER>
+LBM_HD bool collide_delta(const Hot& c, const double* f, const NbrVel& nv, double* df) {
+  double m[16];
+  moments_from_f(f, m);
+  return collide_from_moments<VER>(c, m, 1.0 / m[0], nv, df);
 }
 
 // The collision added to the convection increments `acc`; the new
@@ -197,16 +203,6 @@ template <int VER>
 LBM_HD bool node_update(const Hot& c, const double* f, const double* fxp, const double* fxm, const double* fyp,
                         const double* fym, const NbrVel& nv, double* out) {
   ConvAll<0>::run(c, f, fxp, fxm, fyp, fym, out);
-  return collide_add<VER>(c, f, nv, out);
-}
-
-// New distributions at a node of a one-dimensional problem along AXIS,
-// neighbours fp (+1) and fm (-1) along it: node_update with the other
-// axis's (zero) convection terms left out.
-template <int VER, int AXIS>
-LBM_HD bool node_update_line(const Hot& c, const double* f, const double* fp, const double* fm, const NbrVel& nv,
-                             double* out) {
-  ConvAxis<0, AXIS>::run(c, f, fp, fm, out);
   return collide_add<VER>(c, f, nv, out);
 }
 
