@@ -20,7 +20,7 @@ _LIB_FMA = os.path.join(_HERE, "liblbm_oracle_fma.so")
 # ... and with every dense sum taken in reverse index order.
 _LIB_REV = os.path.join(_HERE, "liblbm_oracle_rev.so")
 # ... and built -O3 -march=native for the host it runs on: the CPU baseline
-# of the benchmark times this build (the parity reference stays the -O2 one).
+# of the benchmark times this variant (the parity reference stays the -O2 one).
 _LIB_NATIVE = os.path.join(_HERE, "liblbm_oracle_native.so")
 _VARIANTS = {"plain": _LIB, "fma": _LIB_FMA, "reversed": _LIB_REV, "native": _LIB_NATIVE}
 _EXTRA = {"plain": [], "fma": ["-mfma", "-ffp-contract=fast"], "reversed": ["-DORACLE_REVERSED_SUMS"],
